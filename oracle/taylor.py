@@ -1,0 +1,224 @@
+"""Dense-matrix Taylor propagation and its A0 derivative (Eqs. (2), (9)-(10), (21), (22)).
+
+Tiny cells only (N_r up to a few hundred): every operator is an explicit
+N_r x N_r matrix per k-point.
+
+Hamiltonian of one step (velocity gauge, Eq. (2); HSE enters through the
+Fock-like term with weight alpha = 1/4, Eq. (8)):
+
+    h_k = T_k[A/c] + diag(v_loc) + alpha * V_x[psi(t_n)]
+    T_k[a] = IDFT diag( |k + G + a|^2 / 2 ) DFT / N_r        (spectral kinetic operator)
+
+Following the paper, h(t + dt/2) is replaced by h(t_n): A = A(t_n) and V_x is
+built from psi(t_n) and frozen for the four Taylor terms. The step is
+
+    psi(t_n + dt) = sum_{m=0}^{4} (-i dt h)^m / m! psi(t_n).
+
+Pulse (Eq. (21)) with A0 the amplitude of A/c:
+    A(t)/c = -A0 cos(w_L t) sin^2(pi t / T_d) e_z   for 0 < t < T_d, else 0.
+
+Energy (Eq. (22) without the ionic/Hartree/PBE pieces, E_GS replaced by the
+energy of the initial state):
+    E[psi; a] = (g_s/N_k)(Omega/N_r) sum conj(psi) (T[a] + v_loc) psi + alpha E_x[psi]
+    E_ex = E[psi(t_N); a(t_N)] - E[psi(t_0); a(t_0)].
+
+dE_ex/dA0 is computed by tangent-linear (forward-mode) propagation, a route
+independent of any reverse-mode code.
+"""
+
+import numpy as np
+
+from .dft import dft3_full
+from .kernel import kernel_table
+from .lattice import reciprocal, volume, gvectors, grid_points
+
+
+def _dft_matrix_full(n):
+    nr = int(np.prod(n))
+    eye = np.eye(nr, dtype=np.complex128).reshape((nr,) + tuple(n))
+    return dft3_full(eye, -1).reshape(nr, nr).T        # column m -> spectrum
+
+
+def kinetic_matrix(n, a, k, avec):
+    """T_k[a] as a dense N_r x N_r matrix acting on flattened periodic parts."""
+    B = reciprocal(a)
+    G = gvectors(n, B).reshape(-1, 3)
+    eps = 0.5 * np.sum((G + np.asarray(k) + np.asarray(avec)) ** 2, axis=1)
+    F = _dft_matrix_full(n)
+    nr = F.shape[0]
+    return (np.conj(F).T @ (eps[:, None] * F)) / nr
+
+
+def kinetic_dmatrix(n, a, k, avec, axis):
+    """d T_k[a] / d a_axis (dense)."""
+    B = reciprocal(a)
+    G = gvectors(n, B).reshape(-1, 3)
+    deps = (G + np.asarray(k) + np.asarray(avec))[:, axis]
+    F = _dft_matrix_full(n)
+    nr = F.shape[0]
+    return (np.conj(F).T @ (deps[:, None] * F)) / nr
+
+
+def exchange_matrix(u, kpts, a, omega, k):
+    """Dense V_x[u] for output k-point k: -(1/N_k) sum_{k'j} u_j(m) C_{kk'}(m - m') conj(u_j(m'))."""
+    u = np.asarray(u, dtype=np.complex128)
+    kpts = np.asarray(kpts, dtype=np.float64).reshape(-1, 3)
+    nk, nb = u.shape[:2]
+    n = u.shape[-3:]
+    nr = int(np.prod(n))
+    B = reciprocal(a)
+    G = gvectors(n, B).reshape(-1, 3)
+    r = grid_points(n, a).reshape(-1, 3)
+    E = np.exp(1j * (r @ G.T))                            # E[m, l] = exp(i G_l . r_m)
+    V = np.zeros((nr, nr), dtype=np.complex128)
+    for kp in range(nk):
+        K = kernel_table(kpts[k] - kpts[kp], k == kp, n, B, omega).reshape(-1)
+        C = (E * K[None, :]) @ np.conj(E).T / nr          # C[m, m'] = (1/N_r) sum_l K_l e^{iG(r_m - r_m')}
+        for j in range(nb):
+            uj = u[kp, j].reshape(-1)
+            V -= (uj[:, None] * C * np.conj(uj)[None, :]) / nk
+    return V
+
+
+def exchange_dmatrix_apply(u, du, kpts, a, omega, k, phi):
+    """Directional derivative of V_x[u] phi along du (real-linear in du)."""
+    u = np.asarray(u, dtype=np.complex128)
+    du = np.asarray(du, dtype=np.complex128)
+    kpts = np.asarray(kpts, dtype=np.float64).reshape(-1, 3)
+    nk, nb = u.shape[:2]
+    n = u.shape[-3:]
+    nr = int(np.prod(n))
+    B = reciprocal(a)
+    G = gvectors(n, B).reshape(-1, 3)
+    r = grid_points(n, a).reshape(-1, 3)
+    E = np.exp(1j * (r @ G.T))
+    out = np.zeros(nr, dtype=np.complex128)
+    phi = phi.reshape(-1)
+    for kp in range(nk):
+        K = kernel_table(kpts[k] - kpts[kp], k == kp, n, B, omega).reshape(-1)
+        C = (E * K[None, :]) @ np.conj(E).T / nr
+        for j in range(nb):
+            uj = u[kp, j].reshape(-1)
+            duj = du[kp, j].reshape(-1)
+            out -= (duj * (C @ (np.conj(uj) * phi)) + uj * (C @ (np.conj(duj) * phi))) / nk
+    return out
+
+
+def pulse_a_over_c(t, A0, omega_l, Td, direction=(0.0, 0.0, 1.0)):
+    """A(t)/c of Eq. (21) with A0 the amplitude of A/c."""
+    if 0.0 < t < Td:
+        s = -A0 * np.cos(omega_l * t) * np.sin(np.pi * t / Td) ** 2
+    else:
+        s = 0.0
+    return s * np.asarray(direction, dtype=np.float64)
+
+
+def step(psi, kpts, a, omega, avec, dt, alpha, vloc=None, order=4):
+    """One Taylor step psi(t_n) -> psi(t_n + dt) with dense h_k (V_x frozen at psi(t_n))."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    nk, nb = psi.shape[:2]
+    n = psi.shape[-3:]
+    out = np.empty_like(psi)
+    for k in range(nk):
+        h = kinetic_matrix(n, a, kpts[k], avec)
+        if vloc is not None:
+            h = h + np.diag(np.asarray(vloc, dtype=np.float64).reshape(-1))
+        if alpha != 0.0:
+            h = h + alpha * exchange_matrix(psi, kpts, a, omega, k)
+        for b in range(nb):
+            x = psi[k, b].reshape(-1)
+            term = x.copy()
+            acc = x.copy()
+            for m in range(1, order + 1):
+                term = (-1j * dt / m) * (h @ term)
+                acc = acc + term
+            out[k, b] = acc.reshape(n)
+    return out
+
+
+def energy(psi, kpts, a, omega, avec, alpha, vloc=None, gs=2.0):
+    psi = np.asarray(psi, dtype=np.complex128)
+    nk = psi.shape[0]
+    n = psi.shape[-3:]
+    nr = int(np.prod(n))
+    w = gs / nk * volume(a) / nr
+    e = 0.0
+    for k in range(nk):
+        h = kinetic_matrix(n, a, kpts[k], avec)
+        if vloc is not None:
+            h = h + np.diag(np.asarray(vloc, dtype=np.float64).reshape(-1))
+        if alpha != 0.0:
+            h = h + 0.5 * alpha * exchange_matrix(psi, kpts, a, omega, k)
+        for b in range(psi.shape[1]):
+            x = psi[k, b].reshape(-1)
+            e += w * np.vdot(x, h @ x)
+    return e
+
+
+def propagate(psi0, kpts, a, omega, A0, dt, nsteps, alpha, omega_l, vloc=None, direction=(0, 0, 1)):
+    """Returns (psi_N, E_ex) for nsteps Taylor steps with the pulse of Eq. (21), T_d = nsteps*dt."""
+    Td = nsteps * dt
+    psi = np.asarray(psi0, dtype=np.complex128)
+    e0 = energy(psi, kpts, a, omega, pulse_a_over_c(0.0, A0, omega_l, Td, direction), alpha, vloc).real
+    for s in range(nsteps):
+        avec = pulse_a_over_c(s * dt, A0, omega_l, Td, direction)
+        psi = step(psi, kpts, a, omega, avec, dt, alpha, vloc)
+    eN = energy(psi, kpts, a, omega, pulse_a_over_c(nsteps * dt, A0, omega_l, Td, direction), alpha, vloc).real
+    return psi, eN - e0
+
+
+def propagate_tangent(psi0, kpts, a, omega, A0, dt, nsteps, alpha, omega_l, vloc=None, direction=(0, 0, 1),
+                      gs=2.0):
+    """Forward-mode derivative dE_ex/dA0 through the same propagation."""
+    Td = nsteps * dt
+    psi = np.asarray(psi0, dtype=np.complex128)
+    nk, nb = psi.shape[:2]
+    n = psi.shape[-3:]
+    nr = int(np.prod(n))
+    dpsi = np.zeros_like(psi)
+    direction = np.asarray(direction, dtype=np.float64)
+    for s in range(nsteps):
+        t = s * dt
+        avec = pulse_a_over_c(t, A0, omega_l, Td, direction)
+        davec = pulse_a_over_c(t, 1.0, omega_l, Td, direction)     # d a / d A0
+        new = np.empty_like(psi)
+        dnew = np.empty_like(psi)
+        for k in range(nk):
+            h = kinetic_matrix(n, a, kpts[k], avec)
+            dT = sum(davec[d] * kinetic_dmatrix(n, a, kpts[k], avec, d) for d in range(3) if davec[d] != 0.0)
+            if isinstance(dT, int):
+                dT = np.zeros((nr, nr), dtype=np.complex128)
+            if vloc is not None:
+                h = h + np.diag(np.asarray(vloc, dtype=np.float64).reshape(-1))
+            if alpha != 0.0:
+                h = h + alpha * exchange_matrix(psi, kpts, a, omega, k)
+            for b in range(nb):
+                x = psi[k, b].reshape(-1)
+                dx = dpsi[k, b].reshape(-1)
+                term, dterm = x.copy(), dx.copy()
+                acc, dacc = x.copy(), dx.copy()
+                for m in range(1, 5):
+                    dh_term = dT @ term
+                    if alpha != 0.0:
+                        dh_term = dh_term + alpha * exchange_dmatrix_apply(psi, dpsi, kpts, a, omega, k, term)
+                    dterm = (-1j * dt / m) * (h @ dterm + dh_term)
+                    term = (-1j * dt / m) * (h @ term)
+                    acc = acc + term
+                    dacc = dacc + dterm
+                new[k, b] = acc.reshape(n)
+                dnew[k, b] = dacc.reshape(n)
+        psi, dpsi = new, dnew
+    # dE(t_N): a(t_N) = 0 and da(t_N)/dA0 = 0, so only psi_N varies
+    aN = pulse_a_over_c(nsteps * dt, A0, omega_l, Td, direction)
+    w = gs / nk * volume(a) / nr
+    de = 0.0
+    for k in range(nk):
+        h = kinetic_matrix(n, a, kpts[k], aN)
+        if vloc is not None:
+            h = h + np.diag(np.asarray(vloc, dtype=np.float64).reshape(-1))
+        if alpha != 0.0:
+            h = h + alpha * exchange_matrix(psi, kpts, a, omega, k)   # d(E_x)/dpsi = 2 w V_x psi (x alpha)
+        for b in range(nb):
+            x = psi[k, b].reshape(-1)
+            de += 2.0 * w * np.real(np.vdot(h @ x, dpsi[k, b].reshape(-1)))
+    return de

@@ -1,0 +1,253 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these compares the oracle with itself: each check uses a closed form,
+a library routine for a special case, an independent route (real-space
+double sum, full DFT matrix, Parseval form), quadrature of the continuum
+Fourier integral, or an exact invariance of the operator.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import erfc
+
+import oracle
+from oracle import kernel as okernel
+from oracle import fock as ofock
+from paper_1507_05156_amd import synth
+from tests.gaussian_wannier import closed_form_ex, bloch_orbitals
+
+A = 10.26
+CELL = np.eye(3) * A
+OMEGA = 0.106
+
+
+def rel(x, y):
+    return float(np.linalg.norm(np.ravel(x - y)) / np.linalg.norm(np.ravel(y)))
+
+
+# ----------------------------------------------------------------- DFT layer
+@pytest.mark.parametrize("shape", [(4, 4, 4), (6, 6, 6), (4, 6, 8), (5, 3, 4)])
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_separable_dft_equals_full_matrix(shape, sign):
+    x = synth.random_fields((2,) + shape, seed=1)
+    assert rel(oracle.dft3(x, sign), oracle.dft3_full(x, sign)) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (6, 8, 10), (16, 16, 16)])
+def test_dft_matches_numpy_fft(shape):
+    x = synth.random_fields((3,) + shape, seed=2)
+    assert rel(oracle.dft3(x, -1), np.fft.fftn(x, axes=(1, 2, 3))) < 1e-13
+    assert rel(oracle.dft3(x, +1), np.fft.ifftn(x, axes=(1, 2, 3)) * np.prod(shape)) < 1e-13
+
+
+# -------------------------------------------------------------- kernel layer
+def test_kernel_small_p_series():
+    """v(p) = (pi/w^2) (1 - x/2 + x^2/6 - x^3/24 + ...), x = p^2 / 4w^2."""
+    for x in [1e-9, 1e-6, 1e-4, 1e-3, 1e-2]:
+        p2 = 4 * OMEGA ** 2 * x
+        series = sum((-x) ** k / math.factorial(k + 1) for k in range(8))
+        ref = np.pi / OMEGA ** 2 * series
+        assert abs(okernel.screened_coulomb_ft(p2, OMEGA) / ref - 1) < 2e-15
+
+
+def test_kernel_is_fourier_transform_of_erfc_over_r():
+    """v(p) = (4 pi / p) int_0^inf erfc(w r) sin(p r) dr (radial transform of erfc(w r)/r)."""
+    for p in [0.05, 0.3, 0.9, 2.5]:
+        # sin(p r) oscillates; integrate the decaying part piecewise over periods
+        f = lambda r: erfc(OMEGA * r) * np.sin(p * r)
+        upper = 60.0 / OMEGA
+        val, err = integrate.quad(f, 0.0, upper, limit=2000, epsabs=1e-14, epsrel=1e-13)
+        ref = 4 * np.pi / p * val
+        assert abs(okernel.screened_coulomb_ft(p * p, OMEGA) / ref - 1) < 1e-9
+
+
+def test_kernel_large_p_is_bare_coulomb():
+    p2 = 4 * OMEGA ** 2 * 60.0
+    assert abs(okernel.screened_coulomb_ft(p2, OMEGA) * p2 / (4 * np.pi) - 1) < 1e-15
+
+
+@pytest.mark.parametrize("n", [(6, 6, 6), (4, 5, 6), (8, 8, 8)])
+def test_kernel_nyquist_symmetry_and_g0(n):
+    """K_{-q}[-l] = K_q[l] (needs the Nyquist average) and K_0[0] = pi/w^2."""
+    B = oracle.reciprocal(CELL)
+    q = np.array([0.13, -0.07, 0.21])
+    Kp = oracle.kernel_table(q, False, n, B, OMEGA)
+    Km = oracle.kernel_table(-q, False, n, B, OMEGA)
+    neg = Km[np.ix_(*[(-np.arange(d)) % d for d in n])]
+    assert np.max(np.abs(neg - Kp) / Kp) < 1e-15
+    K0 = oracle.kernel_table(np.zeros(3), True, n, B, OMEGA)
+    assert K0[0, 0, 0] == pytest.approx(np.pi / OMEGA ** 2, rel=1e-15)
+    assert np.all(K0 > 0)
+
+
+# ------------------------------------------------ Gaussian-Wannier closed form
+@pytest.mark.parametrize("nkm,n,tol", [(1, 32, 1e-10), (2, 32, 1e-13), (2, 24, 1e-11)])
+def test_gaussian_wannier_closed_form(nkm, n, tol):
+    """Pins 4 pi, 1/Omega, the kernel, its q shift, the G=0 term and 1/N_k at once."""
+    kp = synth.gamma_mesh(nkm, CELL)
+    u = bloch_orbitals(n, A, kp, 1.0)
+    e = oracle.exchange_energy(u, kp, CELL, OMEGA)
+    ref = closed_form_ex(1.0, OMEGA, A, nkm)
+    assert abs(e.imag) < 1e-14 * abs(ref)
+    assert abs(e.real - ref) / abs(ref) < tol
+
+
+def test_gaussian_pin_catches_unshifted_kernel(monkeypatch):
+    """A kernel evaluated at |G| instead of |q+G| must fail the k-mesh pin."""
+    orig = okernel.kernel_table
+    monkeypatch.setattr(ofock, "kernel_table", lambda q, z, n, B, w: orig(np.zeros(3), True, n, B, w))
+    kp = synth.gamma_mesh(2, CELL)
+    u = bloch_orbitals(24, A, kp, 1.0)
+    e = ofock.exchange_energy(u, kp, CELL, OMEGA)
+    assert abs(e.real - closed_form_ex(1.0, OMEGA, A, 2)) / abs(e.real) > 1e-3
+
+
+def test_gaussian_pin_catches_missing_four_pi(monkeypatch):
+    orig = okernel.kernel_table
+    monkeypatch.setattr(ofock, "kernel_table", lambda *a: orig(*a) / (4 * np.pi))
+    kp = synth.gamma_mesh(1, CELL)
+    u = bloch_orbitals(24, A, kp, 1.0)
+    e = ofock.exchange_energy(u, kp, CELL, OMEGA)
+    assert abs(e.real - closed_form_ex(1.0, OMEGA, A, 1)) / abs(e.real) > 0.5
+
+
+# ----------------------------------------------------------- G = 0 closed form
+def test_g0_term_closed_form(monkeypatch):
+    """E_x(K) - E_x(K with K_0[0] = 0) = -(g_s/2) N_b pi / (w^2 Omega N_k) for orthonormal orbitals."""
+    cell, kp, u = synth.workload(0, n=8, nk=2, nb=3)
+    e_full = oracle.exchange_energy(u, kp, cell, OMEGA).real
+    orig = okernel.kernel_table
+
+    def no_g0(q, q_is_zero, n, B, w):
+        K = orig(q, q_is_zero, n, B, w)
+        if q_is_zero:
+            K = K.copy()
+            K[0, 0, 0] = 0.0
+        return K
+
+    monkeypatch.setattr(ofock, "kernel_table", no_g0)
+    e_cut = ofock.exchange_energy(u, kp, cell, OMEGA).real
+    nk, nb = u.shape[:2]
+    ref = -(2.0 / 2) * nb * np.pi / (OMEGA ** 2 * oracle.volume(cell) * nk)
+    assert abs((e_full - e_cut) / ref - 1) < 1e-12
+
+
+# ------------------------------------------------------- independent routes
+def test_energy_parseval_route():
+    cell, kp, u = synth.workload(0, n=8, nk=2, nb=3)
+    e1 = oracle.exchange_energy(u, kp, cell, OMEGA)
+    e2 = oracle.exchange_energy_parseval(u, kp, cell, OMEGA)
+    assert abs(e1 - e2) / abs(e2) < 1e-13
+
+
+def test_realspace_double_sum_route():
+    """Eq. (14) as an O(N_r^2) real-space sum equals the Fourier route of Eq. (15)."""
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(4, cell, kp, 2, seed=5, ecut=40.0)
+    phi = synth.random_fields(u.shape, seed=6)
+    v_fourier = oracle.fock_apply(u, phi, kp, cell, OMEGA)
+    v_real = oracle.fock_apply_realspace(u, phi, kp, cell, OMEGA)
+    assert rel(v_real, v_fourier) < 1e-12
+
+
+def test_full_dft_route():
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 2, 1)
+    u = synth.orbitals((4, 6, 4), cell, kp, 2, seed=7, ecut=40.0)
+    phi = synth.random_fields(u.shape, seed=8)
+    assert rel(oracle.fock_apply(u, phi, kp, cell, OMEGA, full_dft=True),
+               oracle.fock_apply(u, phi, kp, cell, OMEGA)) < 1e-13
+
+
+def test_gamma_single_band_screened_poisson():
+    """Gamma, one band: V_x u = -u * IFFT(K_0 FFT|u|^2) / N_r (numpy FFT as the library route)."""
+    cell = np.eye(3) * A
+    kp = np.zeros((1, 3))
+    u = synth.orbitals(12, cell, kp, 1, seed=9)
+    B = oracle.reciprocal(cell)
+    K0 = oracle.kernel_table(np.zeros(3), True, (12, 12, 12), B, OMEGA)
+    ref = -u[0, 0] * np.fft.ifftn(K0 * np.fft.fftn(np.abs(u[0, 0]) ** 2))
+    assert rel(oracle.fock_apply(u, u, kp, cell, OMEGA)[0, 0], ref) < 1e-13
+
+
+# -------------------------------------------------------- operator structure
+@pytest.fixture(scope="module")
+def small():
+    cell, kp, u = synth.workload(0, n=8, nk=2, nb=3)
+    return cell, kp, u
+
+
+def _ip(cell, x, y):
+    nr = np.prod(x.shape[-3:])
+    return oracle.volume(cell) / nr * np.sum(np.conj(x) * y)
+
+
+def test_hermitian_and_negative(small):
+    cell, kp, u = small
+    phi = synth.random_fields(u.shape, seed=11)
+    chi = synth.random_fields(u.shape, seed=12)
+    Vphi = oracle.fock_apply(u, phi, kp, cell, OMEGA)
+    Vchi = oracle.fock_apply(u, chi, kp, cell, OMEGA)
+    for k in range(u.shape[0]):
+        for i in range(u.shape[1]):
+            a1 = _ip(cell, phi[k, i], Vchi[k, i])
+            a2 = np.conj(_ip(cell, chi[k, i], Vphi[k, i]))
+            assert abs(a1 - a2) < 1e-13 * abs(a1)
+            d = _ip(cell, phi[k, i], Vphi[k, i])
+            assert d.real < 0 and abs(d.imag) < 1e-13 * abs(d.real)
+    e = oracle.exchange_energy(u, kp, cell, OMEGA)
+    assert e.real < 0 and abs(e.imag) < 1e-14 * abs(e.real)
+
+
+def test_unitary_and_phase_invariance(small):
+    cell, kp, u = small
+    phi = synth.random_fields(u.shape, seed=13)
+    rng = np.random.default_rng(14)
+    urot = np.empty_like(u)
+    for k in range(u.shape[0]):
+        Z = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+        Q, _ = np.linalg.qr(Z)
+        urot[k] = np.einsum("ab,a...->b...", Q, u[k])
+    assert rel(oracle.fock_apply(urot, phi, kp, cell, OMEGA), oracle.fock_apply(u, phi, kp, cell, OMEGA)) < 1e-13
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, size=u.shape[:2]))
+    uph = u * ph[..., None, None, None]
+    assert rel(oracle.fock_apply(uph, phi, kp, cell, OMEGA), oracle.fock_apply(u, phi, kp, cell, OMEGA)) < 1e-13
+    # V_x(U phi) = U V_x(phi): linear in the target orbitals
+    V = oracle.fock_apply(u, phi, kp, cell, OMEGA)
+    U = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))[0]
+    phir = np.einsum("ab,ka...->kb...", U, phi)
+    assert rel(oracle.fock_apply(u, phir, kp, cell, OMEGA), np.einsum("ab,ka...->kb...", U, V)) < 1e-13
+
+
+def test_translation_covariance(small):
+    cell, kp, u = small
+    phi = synth.random_fields(u.shape, seed=15)
+    shift = np.array([3, 1, 6])
+    t = shift / 8.0 @ cell
+    def tr(x):
+        y = np.roll(x, tuple(shift), axis=(2, 3, 4))
+        return y * np.exp(-1j * (kp @ t))[:, None, None, None, None]
+    lhs = oracle.fock_apply(tr(u), tr(phi), kp, cell, OMEGA)
+    rhs = tr(oracle.fock_apply(u, phi, kp, cell, OMEGA))
+    assert rel(lhs, rhs) < 1e-13
+
+
+def test_rows_subset_matches_full(small):
+    cell, kp, u = small
+    full = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    rows = [(1, 2), (0, 0)]
+    part = oracle.fock_apply(u, u, kp, cell, OMEGA, rows=rows)
+    for k, i in rows:
+        assert np.array_equal(part[k, i], full[k, i])
+
+
+def test_sign_mistake_is_caught(monkeypatch, small):
+    """A dropped minus sign (a plausible slip) makes E_x positive: the negativity pin fails."""
+    cell, kp, u = small
+    orig = ofock.general_apply
+    monkeypatch.setattr(ofock, "fock_apply", lambda *a, **k: -orig(a[1], a[0], a[0], *a[2:], **k))
+    assert ofock.exchange_energy(u, kp, cell, OMEGA).real > 0
