@@ -1,0 +1,142 @@
+/*
+ * fockmi -- the HSE screened Fock-like exchange operator on an MI355X (gfx950).
+ *
+ * C ABI of the library libfockmi.so. Every entry point takes plain pointers
+ * and sizes; device pointers are HIP device memory owned by the caller, the
+ * stream argument is a hipStream_t passed as void* (NULL = the default
+ * stream). No entry point frees caller memory. Status codes are returned;
+ * nothing throws across the ABI; fock_last_error() gives a thread-local
+ * message for the last failing call.
+ *
+ * Operation (Sato, Taniguchi, Shinohara, Yabana, Sec. II C "Nonlocal
+ * Fock-like term", Eqs. (14)-(16); HSE composition Eq. (8)):
+ *
+ *   For orbitals given as periodic parts u_{jk}(r_m) on an n1 x n2 x n3 grid
+ *   of the cell, normalised to (Omega/N_r) sum_m |u|^2 = 1, and target fields
+ *   phi_{ik} at the same k-points,
+ *
+ *     W    = (1/N_r) IDFT( K_{k-k'} * DFT( conj(u_{jk'}) * phi_{ik} ) )
+ *     (V_x phi)_{ik} = -(1/N_k) sum_{k', j} u_{jk'} * W
+ *
+ *   with the erfc-screened kernel K_q[l] = v(q + G_l),
+ *     v(p) = 4 pi/|p|^2 (1 - exp(-|p|^2 / 4 w^2)),  v(0) = pi / w^2,
+ *   q = k - k' never folded, G_l in FFT (fftfreq) order, and kernel entries
+ *   on a Nyquist slot (l_d = -n_d/2) averaged over l_d = +-n_d/2.
+ *   The exchange energy (E_xc piece of Eq. (22), closed shell) is
+ *     E_x = (g_s/2)(1/N_k)(Omega/N_r) sum_{ik,m} conj(u_{ik}) (V_x u)_{ik}.
+ *
+ * Data layout of every orbital array: [k][band][m1][m2][m3], m3 fastest,
+ * interleaved complex128 (re, im) in the cell's real-space grid, 16-byte
+ * aligned. All k-points of a cell are present in every array.
+ */
+#ifndef FOCKMI_H
+#define FOCKMI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fockmi_plan_s* fockmi_plan;
+
+typedef enum {
+  FOCK_OK = 0,
+  FOCK_WARN_NORM = 1,    /* taylor_step: norm drift above the plan threshold (psi still written) */
+  FOCK_ERR_ARG = -1,     /* null / misaligned pointer, bad index, aliasing, bad scalar */
+  FOCK_ERR_SIZE = -2,    /* grid length outside {16, 20, 24, 32}, or a form that needs a cubic grid */
+  FOCK_ERR_HIP = -3,     /* a HIP runtime call failed (message in fock_last_error) */
+  FOCK_ERR_NOMEM = -4,   /* device allocation failed or exceeded the plan's workspace cap */
+  FOCK_ERR_STATE = -5    /* plan unusable (destroyed, or created on another device) */
+} fock_status;
+
+typedef enum {
+  FOCK_FP64 = 0,         /* plain FP64 path: one stage per kernel through HBM */
+  FOCK_FP32_COMP = 1     /* fused pair kernel: complex64 pair FFTs, FP32 band partial sums,
+                            Neumaier-compensated FP64 accumulation over k' and j */
+} fock_prec;
+
+typedef struct {
+  int n[3];              /* FFT grid, each in {16, 20, 24, 32}; FOCK_FP32_COMP needs n1=n2=n3 */
+  double a[3][3];        /* lattice vectors (bohr), one per row */
+  int nk;                /* number of k-points (>= 1) */
+  const double* kpts;    /* HOST [nk][3] Cartesian k-points (bohr^-1); copied at plan creation */
+  int nb;                /* occupied bands per k-point (all fully occupied) */
+  double omega;          /* screening parameter w (bohr^-1), > 0 */
+  double gs;             /* spin degeneracy used by fock_energy (2 = closed shell) */
+} fock_cell_desc;
+
+/* Creates a plan for ncells cells on the current HIP device. Builds the kernel
+ * tables K_q for every distinct q = k_i - k_j of each cell (FP64 on the GPU;
+ * FP32 copies for FOCK_FP32_COMP). tune_cache_json may be NULL; otherwise it
+ * is a path to the autotuner's JSON cache (read, and written after tuning).
+ * Errors: FOCK_ERR_ARG, FOCK_ERR_SIZE, FOCK_ERR_HIP, FOCK_ERR_NOMEM. */
+fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec prec,
+                             const char* tune_cache_json, fockmi_plan* out);
+
+/* Frees everything the plan owns (never caller memory). NULL is accepted. */
+fock_status fock_plan_destroy(fockmi_plan plan);
+
+/* Eqs. (15)-(16): vphi[k][p] = (V_x[u_occ] phi)[k][p] for p < nphi.
+ *   u_occ : device [nk][nb][N_r] complex128, occupied orbitals
+ *   phi   : device [nk][nphi][N_r] complex128 target fields (may equal u_occ)
+ *   vphi  : device [nk][nphi][N_r] complex128 output, overwritten; must not
+ *           overlap u_occ or phi
+ * Stream-ordered; returns without synchronising. */
+fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
+                       void* vphi, void* stream);
+
+/* Exchange energy of u_occ (the E_xc piece of Eq. (22)) in FP64:
+ *   *ex_re, *ex_im <- E_x (the imaginary part is a check, zero in exact arithmetic).
+ * Host pointers; synchronises the stream. Either output pointer may be NULL. */
+fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* ex_re, double* ex_im,
+                        void* stream);
+
+/* Reverse mode of fock_apply (derived from Eq. (15)). Given the cotangent
+ * g_vphi of vphi (PyTorch convention: dL/dRe + i dL/dIm), writes
+ *   g_phi[k][p] = (V_x[u] g)[k][p]                       (device [nk][nphi][N_r], may be NULL)
+ *   g_u[k'][j]  = -(1/N_k) sum_{k,i} ( g_ik * W_{k'-k}(conj(phi_ik) u_jk')
+ *                                    + phi_ik * W_{k'-k}(conj(g_ik) u_jk') )
+ *                                                          (device [nk][nb][N_r], may be NULL)
+ * Outputs are overwritten and must not overlap the inputs. Stream-ordered. */
+fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
+                     const void* g_vphi, void* g_u_occ, void* g_phi, void* stream);
+
+/* One fourth-order Taylor step (Eqs. (9)-(10), with h(t+dt/2) ~ h(t)):
+ *   psi <- sum_{m=0}^{order} (-i dt h)^m / m! psi,
+ *   h = IDFT(|k+G+A/c|^2/2 DFT .) + v_loc + alpha * V_x[psi(t_n)]   (V_x frozen for the step)
+ *   psi      : device [nk][nb][N_r] complex128, in place
+ *   vloc     : device [N_r] float64 local potential, or NULL
+ *   A_over_c : host [3] vector potential A(t_n)/c (bohr^-1)
+ *   order    : 1..4 (4 is the paper's choice)
+ *   max_norm_dev (host, may be NULL) <- max_{k,b} |(Omega/N_r)||psi_kb||^2 - 1| after the step
+ * Synchronises the stream when max_norm_dev is requested. Returns FOCK_WARN_NORM
+ * when that deviation exceeds 1e-6. */
+fock_status taylor_step(fockmi_plan plan, int cell, void* psi, const double* vloc, const double A_over_c[3],
+                        double dt, double alpha, int order, double* max_norm_dev, void* stream);
+
+/* Reverse mode of taylor_step for the same arguments (psi_n is the state
+ * BEFORE the step). Given g_next, the cotangent of psi(t_n + dt):
+ *   g_psi  : device [nk][nb][N_r] complex128 <- cotangent of psi(t_n), overwritten
+ *   g_a    : host [3] <- d L / d (A/c) of this step (added to nothing; overwritten)
+ * Stream-ordered, synchronises to return g_a. */
+fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const double* vloc,
+                            const double A_over_c[3], double dt, double alpha, int order,
+                            const void* g_next, void* g_psi, double g_a[3], void* stream);
+
+/* Modified Gram-Schmidt in band order, per k-point, in FP64 with the cell
+ * inner product (Omega/N_r) sum conj(a) b (the normalisation that Eq. (15)
+ * assumes for occupied orbitals). psi: device [nk][nb][N_r] complex128 in place. */
+fock_status fock_orthonormalize(fockmi_plan plan, int cell, void* psi, void* stream);
+
+/* All cells of the plan in one persistent launch (FOCK_FP32_COMP plans):
+ * u_occ[c], phi[c], vphi[c] as in fock_apply for cell c, nphi[c] targets.
+ * Host arrays of device pointers, one entry per cell. Stream-ordered. */
+fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
+                               const int* nphi, void* const* vphi, void* stream);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* fock_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,321 @@
+// C ABI of libfockmi: plans, argument checks and dispatch of the device kernels.
+//
+// The operator (Sec. II C, Eqs. (15)-(16)) is run through one general routine,
+//   out[kt][s] = (accumulate ? out : 0) + scale * sum_{ks, b} M[ks][b] * W(P[ks][b], X[kt][s]; K_{kt-ks}),
+// W(p, x; K) = (1/N_r) IDFT(K DFT(conj(p) x)). The forward operator is
+// (X, P, M) = (phi, u, u) with scale = -1/N_k; the reverse-mode formulas use
+// the other role assignments (see fock_vjp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fockmi.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace fockmi;
+
+namespace fockmi {
+
+thread_local std::string g_last_error;
+
+fock_status fail(fock_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+fock_status hip_fail(hipError_t e, const char* where) {
+  return fail(FOCK_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool valid_len(int n) { return n == 16 || n == 20 || n == 24 || n == 32; }
+
+fock_status DevBuf::ensure(size_t need, size_t cap, const char* what) {
+  if (need <= bytes) return FOCK_OK;
+  if (cap && need > cap)
+    return fail(FOCK_ERR_NOMEM, "%s: %zu bytes exceed the plan workspace cap of %zu bytes", what, need, cap);
+  release();
+  hipError_t e = hipMalloc(&ptr, need);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(FOCK_ERR_NOMEM, "%s: hipMalloc(%zu) failed: %s", what, need, hipGetErrorString(e));
+  }
+  bytes = need;
+  return FOCK_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+fock_status Plan::check_ready(int cell) const {
+  if (magic != kMagic) return fail(FOCK_ERR_STATE, "plan is not valid (destroyed or corrupt)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != device)
+    return fail(FOCK_ERR_STATE, "plan was created on device %d, current device is %d", device, dev);
+  if (cell < 0 || cell >= (int)cells.size()) return fail(FOCK_ERR_ARG, "cell index %d out of range", cell);
+  return FOCK_OK;
+}
+
+// ------------------------------------------------------------------ plumbing
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
+                            double scale, bool accumulate, hipStream_t st) {
+  const int nr = c.nr;
+  const size_t per_k = (size_t)ns * nx * nr * sizeof(c128);
+  int kb = (int)std::max<size_t>(1, batch_cap / std::max<size_t>(per_k, 1));
+  kb = std::min(kb, c.nk);
+  kb = std::max(1, std::min(kb, 65535 / std::max(1, ns * nx)));  // grid.y of the batch kernels
+  if ((long)ns * nx > 65535) return fail(FOCK_ERR_SIZE, "too many band pairs per k-point pair (%d x %d)", ns, nx);
+  fock_status s = batch.ensure((size_t)kb * per_k, workspace_cap, "plain-path batch buffer");
+  if (s != FOCK_OK) return s;
+  c128* buf = (c128*)batch.ptr;
+  hipError_t e;
+  for (int k = 0; k < c.nk; ++k) {
+    const c128* Xk = X + (size_t)k * nx * nr;
+    c128* outk = out + (size_t)k * nx * nr;
+    for (int ks0 = 0; ks0 < c.nk; ks0 += kb) {
+      const int nkb = std::min(kb, c.nk - ks0);
+      if ((e = launch_pair_product(buf, Xk, P, ks0, nkb, ns, nx, nr, st)) != hipSuccess)
+        return hip_fail(e, "pair product");
+      if ((e = launch_fft3_plain(buf, nkb * ns * nx, c.geom, -1, st)) != hipSuccess)
+        return hip_fail(e, "forward FFT");
+      if ((e = launch_kernel_mul(buf, (const double*)c.K64.ptr, (const int*)c.qidx.ptr, k, c.nk, ks0, nkb, ns * nx,
+                                 nr, st)) != hipSuccess)
+        return hip_fail(e, "kernel multiply");
+      if ((e = launch_fft3_plain(buf, nkb * ns * nx, c.geom, +1, st)) != hipSuccess)
+        return hip_fail(e, "inverse FFT");
+      if ((e = launch_mac(outk, buf, M, ks0, nkb, ns, nx, nr, scale, (accumulate || ks0 > 0) ? 1 : 0, st)) !=
+          hipSuccess)
+        return hip_fail(e, "accumulate");
+    }
+  }
+  return FOCK_OK;
+}
+
+fock_status Plan::shadow(DevBuf& buf, const c128* src, size_t count, const char* what, hipStream_t st,
+                         const c64** out) {
+  fock_status s = buf.ensure(count * sizeof(c64), workspace_cap, what);
+  if (s != FOCK_OK) return s;
+  hipError_t e = launch_to_c64((c64*)buf.ptr, src, (long)count, st);
+  if (e != hipSuccess) return hip_fail(e, what);
+  *out = (const c64*)buf.ptr;
+  return FOCK_OK;
+}
+
+fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
+                            double scale, bool accumulate, hipStream_t st) {
+  const int nr = c.nr;
+  const c64 *Xs = nullptr, *Ps = nullptr, *Ms = nullptr;
+  fock_status s;
+  if ((s = shadow(shadow_p, P, (size_t)c.nk * ns * nr, "complex64 shadow (P)", st, &Ps)) != FOCK_OK) return s;
+  if (M == P) {
+    Ms = Ps;
+  } else if ((s = shadow(shadow_m, M, (size_t)c.nk * ns * nr, "complex64 shadow (M)", st, &Ms)) != FOCK_OK) {
+    return s;
+  }
+  if (X == P && nx == ns) {
+    Xs = Ps;
+  } else if (X == M && nx == ns) {
+    Xs = Ms;
+  } else if ((s = shadow(shadow_x, X, (size_t)c.nk * nx * nr, "complex64 shadow (X)", st, &Xs)) != FOCK_OK) {
+    return s;
+  }
+  const int nitems = c.nk * nx;
+  if ((s = comp.ensure((size_t)nitems * nr * sizeof(c128), workspace_cap, "compensation buffer")) != FOCK_OK)
+    return s;
+  const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, nitems);
+  if (acc_elems && (s = accs.ensure(acc_elems * sizeof(c64), workspace_cap, "FP32 partial sums")) != FOCK_OK)
+    return s;
+  FusedArgs a{};
+  a.X = Xs;
+  a.P = Ps;
+  a.M = Ms;
+  a.Kt = (const float*)c.Kt.ptr;
+  a.qidx = (const int*)c.qidx.ptr;
+  a.out = out;
+  a.comp = (c128*)comp.ptr;
+  a.accs = (c64*)accs.ptr;
+  a.nk = c.nk;
+  a.nx = nx;
+  a.nb = ns;
+  a.item0 = 0;
+  a.nitems = nitems;
+  a.scale = scale;
+  a.accumulate = accumulate ? 1 : 0;
+  a.xcd_map = xcd_map;
+  hipError_t e = launch_fused_apply(c.geom.n1, a, st);
+  if (e != hipSuccess) return hip_fail(e, "fused pair kernel");
+  return FOCK_OK;
+}
+
+fock_status Plan::general(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
+                          double scale, bool accumulate, hipStream_t st) {
+  if (prec == FOCK_FP32_COMP) return run_fused(c, X, nx, P, M, ns, out, scale, accumulate, st);
+  return run_plain(c, X, nx, P, M, ns, out, scale, accumulate, st);
+}
+
+}  // namespace fockmi
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* fock_last_error(void) { return fockmi::g_last_error.c_str(); }
+
+fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec prec, const char* tune_cache_json,
+                             fockmi_plan* out) {
+  g_last_error.clear();
+  if (!out) return fail(FOCK_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cells || ncells < 1) return fail(FOCK_ERR_ARG, "need at least one cell");
+  if (prec != FOCK_FP64 && prec != FOCK_FP32_COMP) return fail(FOCK_ERR_ARG, "unknown precision %d", (int)prec);
+  for (int ci = 0; ci < ncells; ++ci) {
+    const fock_cell_desc& d = cells[ci];
+    for (int dd = 0; dd < 3; ++dd)
+      if (!valid_len(d.n[dd]))
+        return fail(FOCK_ERR_SIZE, "cell %d: grid length %d not in {16, 20, 24, 32}", ci, d.n[dd]);
+    if (prec == FOCK_FP32_COMP && !(d.n[0] == d.n[1] && d.n[1] == d.n[2]))
+      return fail(FOCK_ERR_SIZE, "cell %d: the fused FP32 form needs a cubic grid (got %d x %d x %d)", ci, d.n[0],
+                  d.n[1], d.n[2]);
+    if (d.nk < 1 || d.nb < 1) return fail(FOCK_ERR_ARG, "cell %d: nk and nb must be >= 1", ci);
+    if (!d.kpts) return fail(FOCK_ERR_ARG, "cell %d: kpts is NULL", ci);
+    if (!(d.omega > 0.0) || !std::isfinite(d.omega)) return fail(FOCK_ERR_ARG, "cell %d: omega must be > 0", ci);
+    if (!(d.gs > 0.0)) return fail(FOCK_ERR_ARG, "cell %d: gs must be > 0", ci);
+    if ((long)d.nk * d.nk > 65535L * 64) return fail(FOCK_ERR_ARG, "cell %d: too many k-points", ci);
+  }
+  Plan* p = new Plan();
+  p->prec = prec;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(FOCK_ERR_HIP, "hipGetDevice failed");
+  }
+  if (tune_cache_json) p->tune_path = tune_cache_json;
+  fock_status s = FOCK_OK;
+  for (int ci = 0; ci < ncells && s == FOCK_OK; ++ci) {
+    p->cells.emplace_back();
+    s = p->init_cell(p->cells.back(), cells[ci], ci);
+  }
+  if (s != FOCK_OK) {
+    std::string msg = g_last_error;
+    p->destroy();
+    delete p;
+    g_last_error = msg;
+    return s;
+  }
+  *out = reinterpret_cast<fockmi_plan>(p);
+  return FOCK_OK;
+}
+
+fock_status fock_plan_destroy(fockmi_plan plan) {
+  if (!plan) return FOCK_OK;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->magic != Plan::kMagic) return fail(FOCK_ERR_STATE, "plan is not valid (destroyed or corrupt)");
+  p->destroy();
+  delete p;
+  return FOCK_OK;
+}
+
+fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi, void* vphi,
+                       void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = p->check_ready(cell);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!u_occ || !phi || !vphi) return fail(FOCK_ERR_ARG, "NULL device pointer");
+  if (!aligned16(u_occ) || !aligned16(phi) || !aligned16(vphi))
+    return fail(FOCK_ERR_ARG, "device pointers must be 16-byte aligned");
+  if (nphi < 1) return fail(FOCK_ERR_ARG, "nphi must be >= 1");
+  const size_t bu = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  const size_t bp = (size_t)c.nk * nphi * c.nr * sizeof(c128);
+  if (overlap(vphi, bp, u_occ, bu) || overlap(vphi, bp, phi, bp))
+    return fail(FOCK_ERR_ARG, "vphi overlaps an input array");
+  const double scale = -1.0 / c.nk;
+  return p->general(c, (const c128*)phi, nphi, (const c128*)u_occ, (const c128*)u_occ, c.nb, (c128*)vphi, scale,
+                    false, (hipStream_t)stream);
+}
+
+fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* ex_re, double* ex_im, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = p->check_ready(cell);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!u_occ) return fail(FOCK_ERR_ARG, "NULL device pointer");
+  if (!aligned16(u_occ)) return fail(FOCK_ERR_ARG, "device pointers must be 16-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t count = (size_t)c.nk * c.nb * c.nr;
+  if ((s = p->vu.ensure(count * sizeof(c128), p->workspace_cap, "energy work array")) != FOCK_OK) return s;
+  if ((s = p->general(c, (const c128*)u_occ, c.nb, (const c128*)u_occ, (const c128*)u_occ, c.nb, (c128*)p->vu.ptr,
+                      -1.0 / c.nk, false, st)) != FOCK_OK)
+    return s;
+  double re = 0, im = 0;
+  if ((s = p->dot((const c128*)u_occ, (const c128*)p->vu.ptr, count, st, &re, &im)) != FOCK_OK) return s;
+  const double w = (c.gs / 2.0) / c.nk * c.vol / c.nr;
+  if (ex_re) *ex_re = w * re;
+  if (ex_im) *ex_im = w * im;
+  return FOCK_OK;
+}
+
+fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi, const void* g_vphi,
+                     void* g_u_occ, void* g_phi, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = p->check_ready(cell);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!u_occ || !phi || !g_vphi) return fail(FOCK_ERR_ARG, "NULL device pointer");
+  if (!aligned16(u_occ) || !aligned16(phi) || !aligned16(g_vphi) || (g_u_occ && !aligned16(g_u_occ)) ||
+      (g_phi && !aligned16(g_phi)))
+    return fail(FOCK_ERR_ARG, "device pointers must be 16-byte aligned");
+  if (nphi < 1) return fail(FOCK_ERR_ARG, "nphi must be >= 1");
+  const size_t bu = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  const size_t bp = (size_t)c.nk * nphi * c.nr * sizeof(c128);
+  if (g_u_occ && (overlap(g_u_occ, bu, u_occ, bu) || overlap(g_u_occ, bu, phi, bp) || overlap(g_u_occ, bu, g_vphi, bp)))
+    return fail(FOCK_ERR_ARG, "g_u_occ overlaps an input array");
+  if (g_phi && (overlap(g_phi, bp, u_occ, bu) || overlap(g_phi, bp, phi, bp) || overlap(g_phi, bp, g_vphi, bp) ||
+                (g_u_occ && overlap(g_phi, bp, g_u_occ, bu))))
+    return fail(FOCK_ERR_ARG, "g_phi overlaps another array");
+  hipStream_t st = (hipStream_t)stream;
+  const double scale = -1.0 / c.nk;
+  const c128* U = (const c128*)u_occ;
+  const c128* F = (const c128*)phi;
+  const c128* G = (const c128*)g_vphi;
+  if (g_phi) {
+    if ((s = p->general(c, G, nphi, U, U, c.nb, (c128*)g_phi, scale, false, st)) != FOCK_OK) return s;
+  }
+  if (g_u_occ) {
+    // targets u (k'), sources (phi or g) at k, kernel K_{k'-k}
+    if ((s = p->general(c, U, c.nb, F, G, nphi, (c128*)g_u_occ, scale, false, st)) != FOCK_OK) return s;
+    if ((s = p->general(c, U, c.nb, G, F, nphi, (c128*)g_u_occ, scale, true, st)) != FOCK_OK) return s;
+  }
+  return FOCK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+// Fused FP32 pair kernel: every step of Eq. (15) for one pair without leaving the CU.
+//
+// One workgroup owns one target field X[kt][s] and runs over all sources
+// (k', j). For each pair it forms rho = conj(P_jk') X (the pair density), does
+// the forward 3D FFT, multiplies by K_{kt-k'} (1/N_r folded into the table),
+// does the inverse FFT and accumulates M_jk' * W. The band sum over j is kept
+// in FP32; after every k' the FP32 partial sum is added to an FP64 running sum
+// with Neumaier compensation, and the final FP64 value is s + c.
+//
+// Layout on chip, cubic grid of length N, N*N threads:
+//   x phase : thread holds the line along n1 at fixed (m2, m3) -> global loads
+//             and stores of neighbouring lanes hit neighbouring addresses;
+//   y phase : the line along n2 at fixed (l1, m3);
+//   z phase : the line along n3 at fixed (l1, l2), where the kernel multiply
+//             happens (the table is stored in this layout, value-major).
+// Each phase transforms its line in registers (fft_reg.hpp); LDS only carries
+// the transposes between phases. When a full complex64 field does not fit in
+// LDS (N = 32), each transpose runs in two rounds over half of the field, with
+// the thread map arranged so that a thread never holds two lines at once.
+#include "kernels.hpp"
+
+namespace fockmi {
+
+template <int N>
+constexpr int fused_nph() {
+  return ((long)N * N * (N + 1) * 8 > 160L * 1024) ? 2 : 1;
+}
+
+int fused_phases(int n) {
+  switch (n) {
+    case 16: return fused_nph<16>();
+    case 20: return fused_nph<20>();
+    case 24: return fused_nph<24>();
+    case 32: return fused_nph<32>();
+    default: return 1;
+  }
+}
+
+#ifndef FOCKMI_LOAD_CHUNK
+#define FOCKMI_LOAD_CHUNK 8
+#endif
+
+template <int N>
+constexpr bool fused_acc_in_regs() {
+  return N <= 24;
+}
+
+namespace {
+
+// loads issued back to back before the scheduler may move work across them
+constexpr int kLoadChunk = FOCKMI_LOAD_CHUNK;
+
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+// occupancy target handed to the register allocator: waves per SIMD that the
+// LDS footprint allows (N = 24 runs one 9-wave workgroup per CU)
+template <int N>
+constexpr int fused_waves_per_eu() {
+  return N == 24 ? 3 : 4;
+}
+
+template <int N>
+__global__ void __launch_bounds__(N * N) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<N>())))
+fused_apply_kernel(FusedArgs a) {
+  constexpr int NT = N * N;
+  constexpr int NR = N * N * N;
+  constexpr int NPH = fused_nph<N>();
+  constexpr int H = N / NPH;       // width of one round of the x<->y transpose (along m3)
+  constexpr int TPG = NT / NPH;    // threads per round
+  constexpr int NBK = N / NPH;     // l1 values per round of the y<->z transpose
+  constexpr bool ACCREG = fused_acc_in_regs<N>();
+  constexpr int LDS_A = N * N * H;
+  constexpr int LDS_B = NBK * N * (N + 1);
+  constexpr int LDS = LDS_A > LDS_B ? LDS_A : LDS_B;
+  __shared__ c64 lds[LDS];
+
+  const int t = threadIdx.x;
+  // round indices are wave-uniform (rounds are whole waves); readfirstlane
+  // lets the compiler branch on them instead of masking lanes
+  const int grp = __builtin_amdgcn_readfirstlane(t / TPG);
+  const int tl = t % TPG;
+  const int hl = tl % H;
+  const int clo = hl + H * grp;  // m3 in the x and y phases, l2 in the z phase
+  const int chi = tl / H;        // m2 in the x phase, l1 in the y and z phases
+  const int gyz = __builtin_amdgcn_readfirstlane(chi / NBK);  // round of the y<->z transpose
+  const int lrow = chi % NBK;
+
+  // work item of this workgroup
+  int b = blockIdx.x;
+  if (a.xcd_map) {
+    const int nwg = gridDim.x;
+    const int q = nwg / 8, rem = nwg % 8;
+    const int x = b % 8, r = b / 8;
+    b = x * q + (x < rem ? x : rem) + r;
+  }
+  const int item = a.item0 + b;
+  const int kt = item / a.nx;
+  const int s = item % a.nx;
+
+  // byte offsets: x-phase element (m1, m2=chi, m3=clo) is at voff_x + m1 * N*N*8;
+  // table and FP32 partial sums are value-major: (v, t) at (v * NT + t) * size
+  const unsigned voff_x = (unsigned)((chi * N + clo) * 8);
+  const unsigned voff_x128 = 2u * voff_x;
+  const unsigned voff_t4 = (unsigned)(t * 4);
+  const unsigned voff_t8 = (unsigned)(t * 8);
+  constexpr unsigned FB64 = NR * 8u;   // bytes of one complex64 field
+  constexpr unsigned FB128 = NR * 16u;
+
+  const rsrc_t rX = make_rsrc(a.X + ((long)kt * a.nx + s) * NR, FB64);
+  const rsrc_t rOut = make_rsrc(a.out + ((long)kt * a.nx + s) * NR, FB128);
+  const rsrc_t rComp = make_rsrc(a.comp + ((long)kt * a.nx + s) * NR, FB128);
+  const rsrc_t rAcc = make_rsrc(ACCREG ? a.X : a.accs + (long)blockIdx.x * NR, ACCREG ? 0u : FB64);
+
+  c64 acc[ACCREG ? N : 1];
+
+  for (int ks = 0; ks < a.nk; ++ks) {
+    const int qi = __builtin_amdgcn_readfirstlane(a.qidx[kt * a.nk + ks]);
+    const rsrc_t rK = make_rsrc(a.Kt + (long)qi * NR, NR * 4u);
+    const bool first_ks = (ks == 0);
+    const bool last_ks = (ks == a.nk - 1);
+    for (int j = 0; j < a.nb; ++j) {
+      const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
+      const rsrc_t rM = make_rsrc(a.M + ((long)ks * a.nb + j) * NR, FB64);
+      c64 v[N];
+#pragma unroll
+      for (int m1 = 0; m1 < N; ++m1) {
+        const unsigned so = (unsigned)(m1 * NT * 8);
+        v[m1] = cmulc(ld_c64(rP, voff_x, so), ld_c64(rX, voff_x, so));
+        if (m1 % kLoadChunk == kLoadChunk - 1) __builtin_amdgcn_sched_barrier(0);
+      }
+      fft<N, -1>(v);
+      // x -> y
+#pragma unroll
+      for (int g = 0; g < NPH; ++g) {
+        if (grp == g) {
+#pragma unroll
+          for (int l1 = 0; l1 < N; ++l1) lds[(l1 * N + chi) * H + hl] = v[l1];
+        }
+        __syncthreads();
+        if (grp == g) {
+#pragma unroll
+          for (int m2 = 0; m2 < N; ++m2) v[m2] = lds[(chi * N + m2) * H + hl];
+        }
+        __syncthreads();
+      }
+      fft<N, -1>(v);
+      // y -> z
+#pragma unroll
+      for (int g = 0; g < NPH; ++g) {
+        if (gyz == g) {
+#pragma unroll
+          for (int l2 = 0; l2 < N; ++l2) lds[(lrow * N + l2) * (N + 1) + clo] = v[l2];
+        }
+        __syncthreads();
+        if (gyz == g) {
+#pragma unroll
+          for (int m3 = 0; m3 < N; ++m3) v[m3] = lds[(lrow * N + clo) * (N + 1) + m3];
+        }
+        __syncthreads();
+      }
+      fft<N, -1>(v);
+#pragma unroll
+      for (int l3 = 0; l3 < N; ++l3) v[l3] = cscale(v[l3], ld_f32(rK, voff_t4, (unsigned)(l3 * NT * 4)));
+      fft<N, +1>(v);
+      // z -> y
+#pragma unroll
+      for (int g = 0; g < NPH; ++g) {
+        if (gyz == g) {
+#pragma unroll
+          for (int m3 = 0; m3 < N; ++m3) lds[(lrow * N + clo) * (N + 1) + m3] = v[m3];
+        }
+        __syncthreads();
+        if (gyz == g) {
+#pragma unroll
+          for (int l2 = 0; l2 < N; ++l2) v[l2] = lds[(lrow * N + l2) * (N + 1) + clo];
+        }
+        __syncthreads();
+      }
+      fft<N, +1>(v);
+      // y -> x
+#pragma unroll
+      for (int g = 0; g < NPH; ++g) {
+        if (grp == g) {
+#pragma unroll
+          for (int m2 = 0; m2 < N; ++m2) lds[(chi * N + m2) * H + hl] = v[m2];
+        }
+        __syncthreads();
+        if (grp == g) {
+#pragma unroll
+          for (int l1 = 0; l1 < N; ++l1) v[l1] = lds[(l1 * N + chi) * H + hl];
+        }
+        __syncthreads();
+      }
+      fft<N, +1>(v);
+
+      const bool last_j = (j == a.nb - 1);
+#pragma unroll
+      for (int m1 = 0; m1 < N; ++m1) {
+        const unsigned so = (unsigned)(m1 * NT * 8);
+        if (m1 % kLoadChunk == 0) __builtin_amdgcn_sched_barrier(0);
+        const c64 prod = cmul(ld_c64(rM, voff_x, so), v[m1]);
+        c64 tot;
+        if constexpr (ACCREG) {
+          tot = (j == 0) ? prod : acc[m1] + prod;
+          acc[m1] = tot;
+        } else {
+          tot = (j == 0) ? prod : ld_c64(rAcc, voff_t8, so) + prod;
+          if (!last_j) st_c64(tot, rAcc, voff_t8, so);
+        }
+        v[m1] = tot;
+      }
+      if (last_j) {
+        // fold the FP32 band sum of this k' into the FP64 running sum
+#pragma unroll
+        for (int m1 = 0; m1 < N; ++m1) {
+          const unsigned so = (unsigned)(m1 * NT * 16);
+          if (m1 % kLoadChunk == 0) __builtin_amdgcn_sched_barrier(0);
+          const double xr = a.scale * (double)v[m1].re;
+          const double xi = a.scale * (double)v[m1].im;
+          double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
+          if (!first_ks || a.accumulate) {
+            const c128 o = ld_c128(rOut, voff_x128, so);
+            sr = o.re;
+            si = o.im;
+          }
+          if (!first_ks) {
+            const c128 c = ld_c128(rComp, voff_x128, so);
+            cr = c.re;
+            ci = c.im;
+          }
+          neumaier(sr, cr, xr);
+          neumaier(si, ci, xi);
+          if (last_ks) {
+            st_c128(c128{sr + cr, si + ci}, rOut, voff_x128, so);
+          } else {
+            st_c128(c128{sr, si}, rOut, voff_x128, so);
+            st_c128(c128{cr, ci}, rComp, voff_x128, so);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_n(const FusedArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(fused_apply_kernel<N>, dim3(a.nitems), dim3(N * N), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t fused_acc_scratch_elems(int n, int nitems) {
+  switch (n) {
+    case 32: return fused_acc_in_regs<32>() ? 0 : (size_t)nitems * 32 * 32 * 32;
+    default: return 0;
+  }
+}
+
+hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st) {
+  switch (n) {
+    case 16: return launch_n<16>(a, st);
+    case 20: return launch_n<20>(a, st);
+    case 24: return launch_n<24>(a, st);
+    case 32: return launch_n<32>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fockmi

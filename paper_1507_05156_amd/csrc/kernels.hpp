@@ -1,0 +1,66 @@
+// Launchers of the device kernels (host-callable, stream-ordered).
+// Every launcher returns the hipError_t of its launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_reg.hpp"
+
+namespace fockmi {
+
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+struct Geom {
+  int n1, n2, n3;
+  double B[3][3];  // reciprocal rows b_d
+};
+
+// ---- kernel tables -------------------------------------------------------
+// K[q][l] = scale * Nyquist-averaged v(qvec[q] + G_l) for q < nq, natural slot order.
+hipError_t launch_build_table_f64(double* K, const double* qvec, const int* qzero, int nq, const Geom& g,
+                                  double omega, double scale, hipStream_t st);
+// Fused-layout FP32 copy for a cubic grid of length n (value index l3, thread t).
+hipError_t launch_build_table_fused(float* Kt, const double* K, int nq, int n, hipStream_t st);
+
+// ---- plain FP64 path -----------------------------------------------------
+// batch[((kb*nb + j)*nx + s)][r] = conj(P[ks0+kb][j][r]) * X_k[s][r]
+hipError_t launch_pair_product(c128* batch, const c128* Xk, const c128* P, int ks0, int nkb, int nb, int nx,
+                               int nr, hipStream_t st);
+// in-place 3D FFT of nfields fields of shape n1 x n2 x n3 (sign -1 forward, +1 inverse, unnormalised)
+hipError_t launch_fft3_plain(c128* data, int nfields, const Geom& g, int sign, hipStream_t st);
+// batch[p][l] *= K[qidx[k*nk + ks0 + kb(p)]][l]
+hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int k, int nk, int ks0, int nkb,
+                             int per_kb, int nr, hipStream_t st);
+// out_k[s][r] = (accumulate ? out_k[s][r] : 0) + scale * sum_{kb,j} M[ks0+kb][j][r] * batch[(kb*nb+j)*nx+s][r]
+hipError_t launch_mac(c128* outk, const c128* batch, const c128* M, int ks0, int nkb, int nb, int nx, int nr,
+                      double scale, int accumulate, hipStream_t st);
+
+// ---- fused FP32 path -----------------------------------------------------
+struct FusedArgs {
+  const c64* X;       // [nk][nx][nr] targets
+  const c64* P;       // [nk][nb][nr] conjugated in the pair density
+  const c64* M;       // [nk][nb][nr] multiplier
+  const float* Kt;    // [nq][nr] fused layout, 1/N_r folded
+  const int* qidx;    // [nk][nk] table of (target k, source k')
+  c128* out;          // [nk][nx][nr] FP64 result (running sum)
+  c128* comp;         // [nk][nx][nr] FP64 Neumaier compensation
+  c64* accs;          // per-workgroup FP32 partial sums when they do not fit in registers
+  int nk, nx, nb;
+  int item0, nitems;  // work items [item0, item0 + nitems) of nk*nx
+  double scale;       // -1/N_k
+  int accumulate;     // 1: add to the existing out
+  int xcd_map;        // 1: map workgroups so that one XCD runs the targets of one k
+};
+// n in {16, 20, 24, 32}; returns hipErrorInvalidValue otherwise
+hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st);
+size_t fused_acc_scratch_elems(int n, int nitems);  // c64 elements needed in accs (0 if registers)
+
+// ---- helpers ---------------------------------------------------------------
+hipError_t launch_to_c64(c64* dst, const c128* src, long count, hipStream_t st);
+// partial[b] for b < nblk, then dst[0..1] = sum conj(a) b (re, im), fixed order
+hipError_t launch_dot(double* dst, double* partial, int nblk, const c128* a, const c128* b, long count,
+                      hipStream_t st);
+hipError_t launch_scale_add(c128* y, const c128* x, double sre, double sim, long count, hipStream_t st);
+
+}  // namespace fockmi

@@ -1,0 +1,107 @@
+// Small FP64 helpers: complex64 shadows, a deterministic inner product, axpy.
+#include "kernels.hpp"
+
+namespace fockmi {
+
+namespace {
+
+__global__ void to_c64_kernel(c64* __restrict__ dst, const c128* __restrict__ src, long count) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+    const c128 v = src[i];
+    dst[i] = c64{(float)v.re, (float)v.im};
+  }
+}
+
+constexpr int kDotThreads = 256;
+
+// partial[b] = sum over a fixed grid-stride slice of conj(a) * b, tree-reduced in a fixed order
+__global__ void __launch_bounds__(kDotThreads) dot_partial_kernel(double* __restrict__ partial,
+                                                                  const c128* __restrict__ a,
+                                                                  const c128* __restrict__ b, long count) {
+  __shared__ double sre[kDotThreads], sim[kDotThreads];
+  double re = 0.0, im = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+    const c128 x = a[i], y = b[i];
+    re += x.re * y.re + x.im * y.im;
+    im += x.re * y.im - x.im * y.re;
+  }
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sre[threadIdx.x] += sre[threadIdx.x + w];
+      sim[threadIdx.x] += sim[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sre[0];
+    partial[2 * blockIdx.x + 1] = sim[0];
+  }
+}
+
+__global__ void __launch_bounds__(kDotThreads) dot_final_kernel(double* __restrict__ dst,
+                                                                const double* __restrict__ partial, int nblk) {
+  __shared__ double sre[kDotThreads], sim[kDotThreads];
+  double re = 0.0, im = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kDotThreads) {
+    re += partial[2 * i];
+    im += partial[2 * i + 1];
+  }
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sre[threadIdx.x] += sre[threadIdx.x + w];
+      sim[threadIdx.x] += sim[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dst[0] = sre[0];
+    dst[1] = sim[0];
+  }
+}
+
+__global__ void scale_add_kernel(c128* __restrict__ y, const c128* __restrict__ x, double sre, double sim,
+                                 long count) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+    const c128 v = x[i];
+    c128 o = y[i];
+    o.re += sre * v.re - sim * v.im;
+    o.im += sre * v.im + sim * v.re;
+    y[i] = o;
+  }
+}
+
+unsigned grid_for(long count, int bs) {
+  long g = (count + bs - 1) / bs;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_to_c64(c64* dst, const c128* src, long count, hipStream_t st) {
+  hipLaunchKernelGGL(to_c64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(double* dst, double* partial, int nblk, const c128* a, const c128* b, long count,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(nblk), dim3(kDotThreads), 0, st, partial, a, b, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kDotThreads), 0, st, dst, partial, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_add(c128* y, const c128* x, double sre, double sim, long count, hipStream_t st) {
+  hipLaunchKernelGGL(scale_add_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, y, x, sre, sim, count);
+  return hipGetLastError();
+}
+
+}  // namespace fockmi

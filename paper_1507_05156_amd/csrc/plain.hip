@@ -1,0 +1,200 @@
+// Plain FP64 path: the steps of Eq. (15) one kernel at a time, through HBM.
+//
+//   pair product  rho = conj(u_jk') * phi_ik      (launch_pair_product)
+//   forward DFT   along n1, n2, n3               (launch_fft3_plain, sign -1)
+//   kernel        rho_hat *= K_{k-k'} / N_r       (launch_kernel_mul)
+//   inverse DFT   along n3, n2, n1               (launch_fft3_plain, sign +1)
+//   accumulate    out_ik += scale * sum u_jk' W   (launch_mac)
+//
+// Each FFT pass gives one thread one grid line, transformed in registers.
+// Lines along n1 and n2 are strided, so neighbouring lanes take neighbouring
+// lines and every load is coalesced; lines along n3 are contiguous and are
+// staged through LDS so that the global loads stay coalesced.
+#include "kernels.hpp"
+
+namespace fockmi {
+
+namespace {
+
+__global__ void pair_product_kernel(c128* __restrict__ batch, const c128* __restrict__ Xk,
+                                    const c128* __restrict__ P, int ks0, int nb, int nx, int nr) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;  // (kb*nb + j)*nx + s
+  if (r >= nr) return;
+  const int s = p % nx;
+  const int kbj = p / nx;  // kb*nb + j
+  const c128 x = Xk[(long)s * nr + r];
+  const c128 u = P[((long)ks0 * nb + kbj) * nr + r];
+  batch[(long)p * nr + r] = cmulc(u, x);
+}
+
+// one thread per line of length N with element stride `inner`; lines are
+// enumerated (outer, inner) with base = outer * N * inner + inner_index
+template <int N, int SIGN>
+__global__ void __launch_bounds__(64) fft_strided_kernel(c128* __restrict__ data, long nlines, int inner, long field_lines,
+                                   long field_elems) {
+  const long L = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= nlines) return;
+  const long f = L / field_lines;
+  const long li = L % field_lines;
+  const long base = f * field_elems + (li / inner) * (long)N * inner + (li % inner);
+  c128 v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = data[base + (long)i * inner];
+  fft<N, SIGN>(v);
+#pragma unroll
+  for (int i = 0; i < N; ++i) data[base + (long)i * inner] = v[i];
+}
+
+constexpr int kContigLines = 64;
+
+template <int N, int SIGN>
+__global__ void __launch_bounds__(kContigLines) fft_contig_kernel(c128* __restrict__ data, long nlines) {
+  __shared__ c128 tile[kContigLines * (N + 1)];
+  const long line0 = (long)blockIdx.x * kContigLines;
+  const int tid = threadIdx.x;
+  const long avail = nlines - line0;
+  const int nl = avail < kContigLines ? (int)avail : kContigLines;
+  c128* gbase = data + line0 * N;
+  for (int idx = tid; idx < nl * N; idx += kContigLines) {
+    const int ln = idx / N, pos = idx % N;
+    tile[ln * (N + 1) + pos] = gbase[idx];
+  }
+  __syncthreads();
+  if (tid < nl) {
+    c128 v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = tile[tid * (N + 1) + i];
+    fft<N, SIGN>(v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) tile[tid * (N + 1) + i] = v[i];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nl * N; idx += kContigLines) {
+    const int ln = idx / N, pos = idx % N;
+    gbase[idx] = tile[ln * (N + 1) + pos];
+  }
+}
+
+template <int N, int SIGN>
+hipError_t strided_pass(c128* data, int nfields, int inner, long field_lines, long field_elems, hipStream_t st) {
+  const long nlines = (long)nfields * field_lines;
+  const int bs = 64;
+  hipLaunchKernelGGL((fft_strided_kernel<N, SIGN>), dim3((unsigned)((nlines + bs - 1) / bs)), dim3(bs), 0, st,
+                     data, nlines, inner, field_lines, field_elems);
+  return hipGetLastError();
+}
+
+template <int SIGN>
+hipError_t strided_dispatch(int n, c128* data, int nfields, int inner, long field_lines, long field_elems,
+                            hipStream_t st) {
+  switch (n) {
+    case 16: return strided_pass<16, SIGN>(data, nfields, inner, field_lines, field_elems, st);
+    case 20: return strided_pass<20, SIGN>(data, nfields, inner, field_lines, field_elems, st);
+    case 24: return strided_pass<24, SIGN>(data, nfields, inner, field_lines, field_elems, st);
+    case 32: return strided_pass<32, SIGN>(data, nfields, inner, field_lines, field_elems, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int SIGN>
+hipError_t contig_pass(c128* data, long nlines, hipStream_t st) {
+  hipLaunchKernelGGL((fft_contig_kernel<N, SIGN>), dim3((unsigned)((nlines + kContigLines - 1) / kContigLines)),
+                     dim3(kContigLines), 0, st, data, nlines);
+  return hipGetLastError();
+}
+
+template <int SIGN>
+hipError_t contig_dispatch(int n, c128* data, long nlines, hipStream_t st) {
+  switch (n) {
+    case 16: return contig_pass<16, SIGN>(data, nlines, st);
+    case 20: return contig_pass<20, SIGN>(data, nlines, st);
+    case 24: return contig_pass<24, SIGN>(data, nlines, st);
+    case 32: return contig_pass<32, SIGN>(data, nlines, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+__global__ void kernel_mul_kernel(c128* __restrict__ batch, const double* __restrict__ K,
+                                  const int* __restrict__ qidx, int k, int nk, int ks0, int per_kb, int nr) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (l >= nr) return;
+  const int ks = ks0 + p / per_kb;
+  const double kv = K[(long)qidx[k * nk + ks] * nr + l];
+  c128 v = batch[(long)p * nr + l];
+  v.re *= kv;
+  v.im *= kv;
+  batch[(long)p * nr + l] = v;
+}
+
+__global__ void mac_kernel(c128* __restrict__ outk, const c128* __restrict__ batch, const c128* __restrict__ M,
+                           int ks0, int nkb, int nb, int nx, int nr, double scale, int accumulate) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (r >= nr) return;
+  double are = 0.0, aim = 0.0;
+  for (int kb = 0; kb < nkb; ++kb) {
+    for (int j = 0; j < nb; ++j) {
+      const c128 m = M[((long)(ks0 + kb) * nb + j) * nr + r];
+      const c128 w = batch[((long)(kb * nb + j) * nx + s) * nr + r];
+      are += m.re * w.re - m.im * w.im;
+      aim += m.re * w.im + m.im * w.re;
+    }
+  }
+  c128 o = accumulate ? outk[(long)s * nr + r] : c128{0.0, 0.0};
+  o.re += scale * are;
+  o.im += scale * aim;
+  outk[(long)s * nr + r] = o;
+}
+
+}  // namespace
+
+hipError_t launch_pair_product(c128* batch, const c128* Xk, const c128* P, int ks0, int nkb, int nb, int nx,
+                               int nr, hipStream_t st) {
+  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)(nkb * nb * nx));
+  hipLaunchKernelGGL(pair_product_kernel, grid, dim3(256), 0, st, batch, Xk, P, ks0, nb, nx, nr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft3_plain(c128* data, int nfields, const Geom& g, int sign, hipStream_t st) {
+  const long fe = (long)g.n1 * g.n2 * g.n3;
+  hipError_t e = hipSuccess;
+  // axis 1 (stride n2*n3): lines (m2, m3); axis 2 (stride n3): lines (m1, m3); axis 3 contiguous
+  auto ax1 = [&](int s) {
+    return s < 0 ? strided_dispatch<-1>(g.n1, data, nfields, g.n2 * g.n3, (long)g.n2 * g.n3, fe, st)
+                 : strided_dispatch<+1>(g.n1, data, nfields, g.n2 * g.n3, (long)g.n2 * g.n3, fe, st);
+  };
+  auto ax2 = [&](int s) {
+    return s < 0 ? strided_dispatch<-1>(g.n2, data, nfields, g.n3, (long)g.n1 * g.n3, fe, st)
+                 : strided_dispatch<+1>(g.n2, data, nfields, g.n3, (long)g.n1 * g.n3, fe, st);
+  };
+  auto ax3 = [&](int s) {
+    const long nl = (long)nfields * g.n1 * g.n2;
+    return s < 0 ? contig_dispatch<-1>(g.n3, data, nl, st) : contig_dispatch<+1>(g.n3, data, nl, st);
+  };
+  if (sign < 0) {
+    if ((e = ax1(-1)) != hipSuccess) return e;
+    if ((e = ax2(-1)) != hipSuccess) return e;
+    return ax3(-1);
+  }
+  if ((e = ax3(+1)) != hipSuccess) return e;
+  if ((e = ax2(+1)) != hipSuccess) return e;
+  return ax1(+1);
+}
+
+hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int k, int nk, int ks0, int nkb,
+                             int per_kb, int nr, hipStream_t st) {
+  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)(nkb * per_kb));
+  hipLaunchKernelGGL(kernel_mul_kernel, grid, dim3(256), 0, st, batch, K, qidx, k, nk, ks0, per_kb, nr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac(c128* outk, const c128* batch, const c128* M, int ks0, int nkb, int nb, int nx, int nr,
+                      double scale, int accumulate, hipStream_t st) {
+  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)nx);
+  hipLaunchKernelGGL(mac_kernel, grid, dim3(256), 0, st, outk, batch, M, ks0, nkb, nb, nx, nr, scale, accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace fockmi

@@ -1,0 +1,148 @@
+// Plan set-up: geometry, the distinct pair momenta q = k_t - k_s of a cell and
+// the kernel tables K_q (built on the GPU in FP64, see table.hip).
+#include <cmath>
+#include <cstdlib>
+#include <map>
+#include <tuple>
+
+#include "plan.hpp"
+
+namespace fockmi {
+
+namespace {
+
+void reciprocal_rows(const double a[3][3], double B[3][3], double* vol) {
+  // B = 2 pi inv(a)^T, rows b_d with a_i . b_j = 2 pi delta_ij
+  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  *vol = std::fabs(det);
+  double inv[3][3];
+  inv[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) / det;
+  inv[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) / det;
+  inv[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) / det;
+  inv[1][0] = (a[1][2] * a[2][0] - a[1][0] * a[2][2]) / det;
+  inv[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) / det;
+  inv[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) / det;
+  inv[2][0] = (a[1][0] * a[2][1] - a[1][1] * a[2][0]) / det;
+  inv[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) / det;
+  inv[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) B[i][j] = 2.0 * M_PI * inv[j][i];
+}
+
+}  // namespace
+
+fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
+  if (const char* capenv = std::getenv("FOCKMI_WORKSPACE_CAP")) workspace_cap = (size_t)std::strtoull(capenv, 0, 10);
+  c.geom.n1 = d.n[0];
+  c.geom.n2 = d.n[1];
+  c.geom.n3 = d.n[2];
+  c.nr = d.n[0] * d.n[1] * d.n[2];
+  c.nk = d.nk;
+  c.nb = d.nb;
+  c.omega = d.omega;
+  c.gs = d.gs;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) c.a[i][j] = d.a[i][j];
+  reciprocal_rows(c.a, c.geom.B, &c.vol);
+  if (!(c.vol > 0.0) || !std::isfinite(c.vol)) return fail(FOCK_ERR_ARG, "cell %d: singular lattice", index);
+  c.kpts.assign(d.kpts, d.kpts + 3 * (size_t)d.nk);
+  for (double v : c.kpts)
+    if (!std::isfinite(v)) return fail(FOCK_ERR_ARG, "cell %d: non-finite k-point", index);
+
+  // distinct q = k_t - k_s; q = 0 exactly when t == s (distinct k-points required)
+  double bscale = 0.0;
+  for (int i = 0; i < 3; ++i)
+    bscale = std::fmax(bscale, std::sqrt(c.geom.B[i][0] * c.geom.B[i][0] + c.geom.B[i][1] * c.geom.B[i][1] +
+                                         c.geom.B[i][2] * c.geom.B[i][2]));
+  const double tol = 1e-13 * bscale;
+  std::map<std::tuple<long long, long long, long long>, int> seen;
+  std::vector<double> qv;
+  std::vector<int> qz;
+  c.qidx_host.assign((size_t)c.nk * c.nk, -1);
+  for (int t = 0; t < c.nk; ++t) {
+    for (int s = 0; s < c.nk; ++s) {
+      double q[3];
+      for (int dd = 0; dd < 3; ++dd) q[dd] = c.kpts[3 * t + dd] - c.kpts[3 * s + dd];
+      if (t != s && std::fabs(q[0]) <= tol && std::fabs(q[1]) <= tol && std::fabs(q[2]) <= tol)
+        return fail(FOCK_ERR_ARG, "cell %d: k-points %d and %d coincide", index, t, s);
+      auto key = std::make_tuple(std::llround(q[0] / tol), std::llround(q[1] / tol), std::llround(q[2] / tol));
+      if (t == s) key = std::make_tuple(0LL, 0LL, 0LL);
+      auto it = seen.find(key);
+      int id;
+      if (it == seen.end()) {
+        id = (int)qz.size();
+        seen.emplace(key, id);
+        for (int dd = 0; dd < 3; ++dd) qv.push_back(t == s ? 0.0 : q[dd]);
+        qz.push_back(t == s ? 1 : 0);
+      } else {
+        id = it->second;
+      }
+      c.qidx_host[(size_t)t * c.nk + s] = id;
+    }
+  }
+  c.nq = (int)qz.size();
+
+  fock_status s;
+  if ((s = c.qidx.ensure(c.qidx_host.size() * sizeof(int), 0, "q index table")) != FOCK_OK) return s;
+  if ((s = c.qvec.ensure(qv.size() * sizeof(double), 0, "q vectors")) != FOCK_OK) return s;
+  if ((s = c.qzero.ensure(qz.size() * sizeof(int), 0, "q flags")) != FOCK_OK) return s;
+  hipError_t e;
+  if ((e = hipMemcpy(c.qidx.ptr, c.qidx_host.data(), c.qidx_host.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_fail(e, "upload q index");
+  if ((e = hipMemcpy(c.qvec.ptr, qv.data(), qv.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "upload q vectors");
+  if ((e = hipMemcpy(c.qzero.ptr, qz.data(), qz.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "upload q flags");
+
+  if ((s = c.K64.ensure((size_t)c.nq * c.nr * sizeof(double), 0, "FP64 kernel tables")) != FOCK_OK) return s;
+  if ((e = launch_build_table_f64((double*)c.K64.ptr, (const double*)c.qvec.ptr, (const int*)c.qzero.ptr, c.nq,
+                                  c.geom, c.omega, 1.0 / c.nr, 0)) != hipSuccess)
+    return hip_fail(e, "kernel table");
+  if (prec == FOCK_FP32_COMP) {
+    if ((s = c.Kt.ensure((size_t)c.nq * c.nr * sizeof(float), 0, "FP32 kernel tables")) != FOCK_OK) return s;
+    if ((e = launch_build_table_fused((float*)c.Kt.ptr, (const double*)c.K64.ptr, c.nq, c.geom.n1, 0)) !=
+        hipSuccess)
+      return hip_fail(e, "FP32 kernel table");
+  }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "plan set-up");
+  return FOCK_OK;
+}
+
+void Plan::destroy() {
+  for (Cell& c : cells) {
+    c.qidx.release();
+    c.qvec.release();
+    c.qzero.release();
+    c.K64.release();
+    c.Kt.release();
+  }
+  for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres}) b->release();
+  if (host_pinned) (void)hipHostFree(host_pinned);
+  host_pinned = nullptr;
+  magic = 0;
+}
+
+fock_status Plan::dot(const c128* a, const c128* b, size_t count, hipStream_t st, double* re, double* im) {
+  const int nblk = 1024;
+  fock_status s;
+  if ((s = partial.ensure(2 * nblk * sizeof(double), 0, "reduction partials")) != FOCK_OK) return s;
+  if ((s = dotres.ensure(2 * sizeof(double), 0, "reduction result")) != FOCK_OK) return s;
+  hipError_t e;
+  if (!host_pinned) {
+    if ((e = hipHostMalloc((void**)&host_pinned, 2 * sizeof(double), 0)) != hipSuccess)
+      return hip_fail(e, "pinned host buffer");
+  }
+  if ((e = launch_dot((double*)dotres.ptr, (double*)partial.ptr, nblk, a, b, (long)count, st)) != hipSuccess)
+    return hip_fail(e, "reduction");
+  if ((e = hipMemcpyAsync(host_pinned, dotres.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(e, "reduction copy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "reduction sync");
+  *re = host_pinned[0];
+  *im = host_pinned[1];
+  return FOCK_OK;
+}
+
+}  // namespace fockmi

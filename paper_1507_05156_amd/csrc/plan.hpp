@@ -1,0 +1,66 @@
+// Plan object behind the opaque fockmi_plan handle (host side only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fockmi.h"
+#include "kernels.hpp"
+
+namespace fockmi {
+
+fock_status fail(fock_status st, const char* fmt, ...);
+fock_status hip_fail(hipError_t e, const char* where);
+
+// device allocation owned by the plan, grown on demand
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  fock_status ensure(size_t need, size_t cap, const char* what);
+  void release();
+};
+
+struct Cell {
+  Geom geom{};
+  int nr = 0, nk = 0, nb = 0;
+  double a[3][3]{}, vol = 0.0, omega = 0.0, gs = 2.0;
+  std::vector<double> kpts;   // [nk][3]
+  int nq = 0;                 // distinct q = k_t - k_s
+  std::vector<int> qidx_host; // [nk][nk]
+  DevBuf qidx, qvec, qzero;   // int[nk*nk], double[nq*3], int[nq]
+  DevBuf K64;                 // double[nq][nr], 1/N_r folded, natural slot order
+  DevBuf Kt;                  // float[nq][nr], fused-kernel layout (FP32 plans)
+};
+
+struct Plan {
+  static constexpr unsigned kMagic = 0xF0C4C0DEu;
+  unsigned magic = kMagic;
+  fock_prec prec = FOCK_FP64;
+  int device = 0;
+  std::string tune_path;
+  std::vector<Cell> cells;
+  size_t workspace_cap = 0;                 // 0 = no cap (FOCKMI_WORKSPACE_CAP overrides)
+  size_t batch_cap = size_t(1) << 30;       // plain path: bytes per pair batch
+  int xcd_map = 1;
+  DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres;
+  double* host_pinned = nullptr;            // 2 doubles for reductions
+
+  fock_status init_cell(Cell& c, const fock_cell_desc& d, int index);
+  fock_status check_ready(int cell) const;
+  void destroy();
+
+  fock_status general(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
+                      double scale, bool accumulate, hipStream_t st);
+  fock_status run_plain(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
+                        double scale, bool accumulate, hipStream_t st);
+  fock_status run_fused(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
+                        double scale, bool accumulate, hipStream_t st);
+  fock_status shadow(DevBuf& buf, const c128* src, size_t count, const char* what, hipStream_t st,
+                     const c64** out);
+  // sum conj(a) b over count elements in FP64 (fixed order); synchronises st
+  fock_status dot(const c128* a, const c128* b, size_t count, hipStream_t st, double* re, double* im);
+};
+
+}  // namespace fockmi
