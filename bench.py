@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the screened Fock-like exchange operator on one MI355X.
+
+A step is one full application V_x[u] u over every (k, i, k', j) pair of the
+workload (kernel tables resident, orbitals already in HBM), in the fused FP32
+form (complex64 pair FFTs, FP32 band sums, Neumaier-compensated FP64 k' sums).
+The plain FP64 path runs the same orbitals for the speed-up and the per-k
+error of the FP32 form; the FP64 oracle runs a bounded sample on the host.
+
+Prints one JSON line. Default workload: 32^3 grid, 6x6x6 k-mesh, 16 bands
+(11,943,936 pairs per step).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+
+
+def flops_per_pair(nr: int) -> float:
+    """Nominal algorithmic flops of one pair: two complex 3D FFTs (5 N log2 N each)
+    plus pair product (6), kernel multiply (2) and multiply-accumulate (8) per point."""
+    return 10.0 * nr * math.log2(nr) + 16.0 * nr
+
+
+def cpu_baseline(u, kp, cell, omega, nsrc):
+    """The FP64 oracle on one output row against the first nsrc source k-points."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    us = u[:nsrc]
+    t0 = time.perf_counter()
+    oracle.fock_apply(us, us, kp[:nsrc], cell, omega, rows=[(0, 0)])
+    dt = time.perf_counter() - t0
+    pairs = nsrc * u.shape[1]
+    return pairs / dt, dt, pairs, threads
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2, help="2: 32^3/216k/16b (default); 1: 24^3/64k/16b")
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed plain FP64 applications (0 = skip)")
+    ap.add_argument("--cpu-sources", type=int, default=96, help="source k-points in the oracle sample (0 = skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU decomposition is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1507_05156_amd import synth
+    from paper_1507_05156_amd.api import Plan
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    omega = synth.OMEGA_HSE
+    t_gen = time.perf_counter()
+    cell, kp, u = synth.workload(args.workload)
+    nk, nb, n = u.shape[0], u.shape[1], u.shape[2]
+    nr = n ** 3
+    pairs = (nk * nb) ** 2
+    print(f"[bench] workload {args.workload}: {n}^3 grid, {nk} k, {nb} bands, {pairs} pairs/step "
+          f"(inputs generated in {time.perf_counter() - t_gen:.1f}s)", file=sys.stderr, flush=True)
+    ud = torch.from_numpy(u).to(dev)
+    desc = dict(n=n, a=cell, kpts=kp, nb=nb, omega=omega)
+
+    # ---------------------------------------------------------------- FP32 form
+    plan32 = Plan(desc, prec="fp32")
+    out32 = torch.empty_like(ud)
+    for _ in range(args.warmup):
+        plan32.apply(ud, out=out32)
+    torch.cuda.synchronize()
+    plan32.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        plan32.apply(ud, out=out32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, launches = plan32.profile_read()
+    plan32.profile(False)
+    elapsed = t1 - t0
+    value = args.steps * pairs / elapsed
+    kern_avg_s = kern_ms / 1e3 / max(launches, 1)
+    achieved_tflops = flops_per_pair(nr) * pairs / kern_avg_s / 1e12
+    alg_bytes = pairs * nr * 8.0   # one complex64 orbital streamed per pair
+    print(f"[bench] fp32: {elapsed / args.steps * 1e3:.1f} ms/step, {value:.4e} pairs/s, "
+          f"kernel {kern_avg_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    e32 = plan32.energy(ud)
+
+    # ---------------------------------------------------------- plain FP64 path
+    fp64 = {}
+    if args.fp64_steps > 0:
+        plan64 = Plan(desc, prec="fp64")
+        out64 = torch.empty_like(ud)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            plan64.apply(ud, out=out64)
+        torch.cuda.synchronize()
+        dt64 = (time.perf_counter() - t0) / args.fp64_steps
+        diff = (out32 - out64).reshape(nk, -1).norm(dim=1)
+        refn = out64.reshape(nk, -1).norm(dim=1)
+        rel = (diff / refn).cpu().numpy()
+        w = (2.0 / 2.0) / nk * abs(np.linalg.det(cell)) / nr
+        e64 = (w * torch.vdot(ud.reshape(-1), out64.reshape(-1))).item()
+        fp64 = dict(fp64_plain_pairs_per_s=pairs / dt64, fp64_plain_ms_per_step=dt64 * 1e3,
+                    speedup_fp32_vs_fp64_plain=value / (pairs / dt64),
+                    fp32_max_rel_err_per_k_vs_fp64=float(rel.max()),
+                    fp32_median_rel_err_per_k_vs_fp64=float(np.median(rel)),
+                    ex_fp32=e32.real, ex_fp64=e64.real,
+                    ex_rel_err_fp32_vs_fp64=abs(e32.real - e64.real) / abs(e64.real))
+        print(f"[bench] fp64 plain: {dt64 * 1e3:.1f} ms/step, max per-k rel err of fp32 {rel.max():.2e}",
+              file=sys.stderr, flush=True)
+        del plan64, out64
+
+    # ------------------------------------------------------------ CPU baseline
+    cpu = None
+    if args.cpu_sources > 0:
+        nsrc = min(args.cpu_sources, nk)
+        pps, dt, cpairs, threads = cpu_baseline(u, kp, cell, omega, nsrc)
+        cpu = {"value": pps, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"output row (k=0, i=0) against {nsrc} source k-points x {nb} bands = {cpairs} pairs "
+                         f"of the {n}^3 workload, {dt:.1f} s"}
+        print(f"[bench] cpu oracle: {pps:.1f} pairs/s on {threads} threads", file=sys.stderr, flush=True)
+
+    rec = {
+        "metric": "Fock pair-FFTs/s (pairs/s) of the fused FP32 form, vs plain FP64",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 pair FFTs, fp64 accumulation",
+        "data": "synthetic seeded orbitals",
+        "config": {"workload": f"{n}^3 grid, {round(nk ** (1 / 3))}^3 Gamma-centred k-mesh ({nk} k), {nb} bands, "
+                               f"a=10.26 bohr cubic, omega={omega} bohr^-1",
+                   "pairs_per_step": pairs, "ffts_per_step": 2 * pairs, "kernel": "fused FP32 pair kernel"},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,
+                     "flops_per_pair": flops_per_pair(nr), "pairs_per_launch": pairs,
+                     "hbm_alg_GBs": alg_bytes / kern_avg_s / 1e9,
+                     "hbm_alg_frac": alg_bytes / kern_avg_s / 1e9 / HBM_PEAK_GBS},
+        "ffts_per_s": 2 * value,
+        "cpu_baseline": cpu,
+    }
+    rec.update(fp64)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,15 @@ fock_status fock_orthonormalize(fockmi_plan plan, int cell, void* psi, void* str
 fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
                                const int* nphi, void* const* vphi, void* stream);
 
+/* Diagnostics for measurement. While enabled, every launch of the fused pair
+ * kernel (FOCK_FP32_COMP plans) and every batch of the plain path's pair
+ * pipeline (FOCK_FP64 plans) is bracketed by HIP events recorded on the
+ * caller's stream. fock_profile_read synchronises those events and returns
+ * the summed elapsed time (ms) and the number of bracketed launches; reset=1
+ * clears the record. Enabling costs two event records per launch. */
+fock_status fock_profile_enable(fockmi_plan plan, int enable);
+fock_status fock_profile_read(fockmi_plan plan, double* kernel_ms, long long* launches, int reset);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* fock_last_error(void);
 

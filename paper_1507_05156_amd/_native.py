@@ -26,7 +26,8 @@ FOCK_FP64 = 0
 FOCK_FP32_COMP = 1
 
 EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_energy", "fock_vjp", "taylor_step",
-           "taylor_step_vjp", "fock_orthonormalize", "fock_apply_batched", "fock_last_error"]
+           "taylor_step_vjp", "fock_orthonormalize", "fock_apply_batched", "fock_profile_enable",
+           "fock_profile_read", "fock_last_error"]
 
 
 class CellDesc(C.Structure):
@@ -62,6 +63,8 @@ def lib():
     L.taylor_step_vjp.argtypes = [vp, i, vp, vp, pd, d, d, i, vp, vp, pd, vp]
     L.fock_orthonormalize.argtypes = [vp, i, vp, vp]
     L.fock_apply_batched.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i), C.POINTER(vp), vp]
+    L.fock_profile_enable.argtypes = [vp, i]
+    L.fock_profile_read.argtypes = [vp, pd, C.POINTER(C.c_longlong), i]
     L.fock_last_error.argtypes = []
     L.fock_last_error.restype = C.c_char_p
     for name in EXPORTS[:-1]:

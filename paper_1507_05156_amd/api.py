@@ -92,6 +92,17 @@ class Plan:
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {exp}")
         return t
 
+    def profile(self, enable=True):
+        """Bracket the dominant kernel's launches with HIP events on the caller's stream."""
+        N.check(self._lib.fock_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset=True):
+        """(summed kernel milliseconds, number of bracketed launches)."""
+        ms = C.c_double()
+        n = C.c_longlong()
+        N.check(self._lib.fock_profile_read(self._h, C.byref(ms), C.byref(n), 1 if reset else 0))
+        return ms.value, n.value
+
     # ------------------------------------------------------------- operations
     def apply(self, u, phi=None, cell=0, out=None):
         """V_x[u] phi (phi defaults to u)."""

@@ -94,6 +94,7 @@ fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const
   if (s != FOCK_OK) return s;
   c128* buf = (c128*)batch.ptr;
   hipError_t e;
+  if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
   for (int k = 0; k < c.nk; ++k) {
     const c128* Xk = X + (size_t)k * nx * nr;
     c128* outk = out + (size_t)k * nx * nr;
@@ -113,6 +114,7 @@ fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const
         return hip_fail(e, "accumulate");
     }
   }
+  if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
   return FOCK_OK;
 }
 
@@ -167,8 +169,10 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
   a.scale = scale;
   a.accumulate = accumulate ? 1 : 0;
   a.xcd_map = xcd_map;
-  hipError_t e = launch_fused_apply(c.geom.n1, a, st);
-  if (e != hipSuccess) return hip_fail(e, "fused pair kernel");
+  hipError_t e = prof_begin(st);
+  if (e != hipSuccess) return hip_fail(e, "profile event");
+  if ((e = launch_fused_apply(c.geom.n1, a, st)) != hipSuccess) return hip_fail(e, "fused pair kernel");
+  if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
   return FOCK_OK;
 }
 
@@ -314,6 +318,31 @@ fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* 
     // targets u (k'), sources (phi or g) at k, kernel K_{k'-k}
     if ((s = p->general(c, U, c.nb, F, G, nphi, (c128*)g_u_occ, scale, false, st)) != FOCK_OK) return s;
     if ((s = p->general(c, U, c.nb, G, F, nphi, (c128*)g_u_occ, scale, true, st)) != FOCK_OK) return s;
+  }
+  return FOCK_OK;
+}
+
+fock_status fock_profile_enable(fockmi_plan plan, int enable) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->magic != Plan::kMagic) return fail(FOCK_ERR_STATE, "plan is not valid (destroyed or corrupt)");
+  p->profiling = enable != 0;
+  return FOCK_OK;
+}
+
+fock_status fock_profile_read(fockmi_plan plan, double* kernel_ms, long long* launches, int reset) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->magic != Plan::kMagic) return fail(FOCK_ERR_STATE, "plan is not valid (destroyed or corrupt)");
+  fock_status s = p->prof_collect();
+  if (s != FOCK_OK) return s;
+  if (kernel_ms) *kernel_ms = p->prof_ms;
+  if (launches) *launches = p->prof_launches;
+  if (reset) {
+    p->prof_ms = 0.0;
+    p->prof_launches = 0;
   }
   return FOCK_OK;
 }

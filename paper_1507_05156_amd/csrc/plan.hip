@@ -111,7 +111,45 @@ fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
   return FOCK_OK;
 }
 
+hipError_t Plan::prof_begin(hipStream_t st) {
+  if (!profiling) return hipSuccess;
+  hipEvent_t a, b;
+  hipError_t e = hipEventCreate(&a);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreate(&b)) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return e;
+  }
+  prof_events.emplace_back(a, b);
+  return hipEventRecord(a, st);
+}
+
+hipError_t Plan::prof_end(hipStream_t st) {
+  if (!profiling || prof_events.empty()) return hipSuccess;
+  return hipEventRecord(prof_events.back().second, st);
+}
+
+fock_status Plan::prof_collect() {
+  for (auto& ev : prof_events) {
+    hipError_t e = hipEventSynchronize(ev.second);
+    if (e != hipSuccess) return hip_fail(e, "profile event");
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, ev.first, ev.second)) != hipSuccess) return hip_fail(e, "profile elapsed");
+    prof_ms += ms;
+    ++prof_launches;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  prof_events.clear();
+  return FOCK_OK;
+}
+
 void Plan::destroy() {
+  for (auto& ev : prof_events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  prof_events.clear();
   for (Cell& c : cells) {
     c.qidx.release();
     c.qvec.release();

@@ -46,6 +46,13 @@ struct Plan {
   int xcd_map = 1;
   DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres;
   double* host_pinned = nullptr;            // 2 doubles for reductions
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  double prof_ms = 0.0;
+  long long prof_launches = 0;
+  hipError_t prof_begin(hipStream_t st);
+  hipError_t prof_end(hipStream_t st);
+  fock_status prof_collect();
 
   fock_status init_cell(Cell& c, const fock_cell_desc& d, int index);
   fock_status check_ready(int cell) const;
