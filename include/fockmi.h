@@ -122,6 +122,17 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
                             const double A_over_c[3], double dt, double alpha, int order,
                             const void* g_next, void* g_psi, double g_a[3], void* stream);
 
+/* Energy functional of the propagated state (Eq. (22) restricted to the
+ * pieces built here; E_GS is left to the caller):
+ *   E = (g_s/N_k)(Omega/N_r) sum conj(psi) (T[A/c] + v_loc) psi + alpha * E_x[psi]
+ *   *e_out    (host)   <- E
+ *   grad_psi  (device [nk][nb][N_r] complex128, may be NULL) <- dE/dpsi in the
+ *             PyTorch convention, 2 (g_s/N_k)(Omega/N_r) (T + v_loc + alpha V_x[psi]) psi
+ *   grad_a    (host [3], may be NULL) <- dE/d(A/c) = (g_s/N_k)(Omega/N_r^2) sum_l (k+G_l+A/c) |DFT psi|^2
+ * Synchronises the stream. */
+fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
+                          double alpha, double* e_out, void* grad_psi, double grad_a[3], void* stream);
+
 /* Modified Gram-Schmidt in band order, per k-point, in FP64 with the cell
  * inner product (Omega/N_r) sum conj(a) b (the normalisation that Eq. (15)
  * assumes for occupied orbitals). psi: device [nk][nb][N_r] complex128 in place. */

@@ -222,3 +222,95 @@ def propagate_tangent(psi0, kpts, a, omega, A0, dt, nsteps, alpha, omega_l, vloc
             x = psi[k, b].reshape(-1)
             de += 2.0 * w * np.real(np.vdot(h @ x, dpsi[k, b].reshape(-1)))
     return de
+
+
+# ----------------------------------------------------------- matrix-free forms
+# The same operators applied without forming N_r x N_r matrices (separable naive
+# DFTs for the kinetic term, the Fourier-space exchange operator of fock.py), so
+# that grids of the supported lengths (16^3 and up) stay affordable.
+
+def kinetic_apply(x, kpts, a, avec):
+    """T_k[a] x for x [nk][nb][n1][n2][n3]: IDFT(|k+G+a|^2/2 DFT x)/N_r."""
+    from .dft import dft3
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[-3:]
+    nr = int(np.prod(n))
+    B = reciprocal(a)
+    G = gvectors(n, B)
+    out = np.empty_like(x)
+    for k in range(x.shape[0]):
+        eps = 0.5 * np.sum((G + np.asarray(kpts[k]) + np.asarray(avec)) ** 2, axis=-1)
+        out[k] = dft3(eps * dft3(x[k], -1), +1) / nr
+    return out
+
+
+def kinetic_dapply(x, kpts, a, avec, axis):
+    """(d T_k[a] / d a_axis) x."""
+    from .dft import dft3
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[-3:]
+    nr = int(np.prod(n))
+    B = reciprocal(a)
+    G = gvectors(n, B)
+    out = np.empty_like(x)
+    for k in range(x.shape[0]):
+        d = (G + np.asarray(kpts[k]) + np.asarray(avec))[..., axis]
+        out[k] = dft3(d * dft3(x[k], -1), +1) / nr
+    return out
+
+
+def h_apply(u, x, kpts, a, omega, avec, alpha, vloc=None):
+    """h x with h = T[a] + v_loc + alpha V_x[u]."""
+    from .fock import fock_apply
+    y = kinetic_apply(x, kpts, a, avec)
+    if vloc is not None:
+        y = y + np.asarray(vloc).reshape(x.shape[-3:]) * x
+    if alpha != 0.0:
+        y = y + alpha * fock_apply(u, x, kpts, a, omega)
+    return y
+
+
+def step_matfree(psi, kpts, a, omega, avec, dt, alpha, vloc=None, order=4):
+    psi = np.asarray(psi, dtype=np.complex128)
+    term = psi.copy()
+    acc = psi.copy()
+    for m in range(1, order + 1):
+        term = (-1j * dt / m) * h_apply(psi, term, kpts, a, omega, avec, alpha, vloc)
+        acc = acc + term
+    return acc
+
+
+def step_tangent_matfree(psi, dpsi, davec, kpts, a, omega, avec, dt, alpha, vloc=None, order=4):
+    """Forward-mode derivative of step_matfree along (dpsi, davec)."""
+    from .fock import general_apply
+    psi = np.asarray(psi, dtype=np.complex128)
+    dpsi = np.asarray(dpsi, dtype=np.complex128)
+    term, dterm = psi.copy(), dpsi.copy()
+    dacc = dpsi.copy()
+    for m in range(1, order + 1):
+        dh = sum(davec[d] * kinetic_dapply(term, kpts, a, avec, d) for d in range(3))
+        if alpha != 0.0:
+            # derivative of V_x[u] term in the occupied orbitals (both occurrences)
+            dh = dh + alpha * (general_apply(term, psi, dpsi, kpts, a, omega)
+                               + general_apply(term, dpsi, psi, kpts, a, omega))
+        dterm = (-1j * dt / m) * (h_apply(psi, dterm, kpts, a, omega, avec, alpha, vloc) + dh)
+        term = (-1j * dt / m) * h_apply(psi, term, kpts, a, omega, avec, alpha, vloc)
+        dacc = dacc + dterm
+    return dacc
+
+
+def energy_matfree(psi, kpts, a, omega, avec, alpha, vloc=None, gs=2.0):
+    """E[psi; a] and its gradient in the PyTorch convention."""
+    from .fock import fock_apply
+    psi = np.asarray(psi, dtype=np.complex128)
+    nk = psi.shape[0]
+    nr = int(np.prod(psi.shape[-3:]))
+    w = gs / nk * volume(a) / nr
+    tv = kinetic_apply(psi, kpts, a, avec)
+    if vloc is not None:
+        tv = tv + np.asarray(vloc).reshape(psi.shape[-3:]) * psi
+    vx = fock_apply(psi, psi, kpts, a, omega) if alpha != 0.0 else np.zeros_like(psi)
+    e = w * np.real(np.sum(np.conj(psi) * tv)) + 0.5 * alpha * w * np.real(np.sum(np.conj(psi) * vx))
+    grad = 2.0 * w * (tv + alpha * vx)
+    grad_a = np.array([w * np.real(np.sum(np.conj(psi) * kinetic_dapply(psi, kpts, a, avec, d))) for d in range(3)])
+    return e, grad, grad_a

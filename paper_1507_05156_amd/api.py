@@ -164,6 +164,20 @@ class Plan:
                                           _stream()))
         return gpsi, np.array([ga[0], ga[1], ga[2]])
 
+    def energy_functional(self, psi, a_over_c, alpha, vloc=None, cell=0, want_grad=False):
+        """E[psi; a] = (g_s/N_k)(Omega/N_r) sum conj(psi)(T[a] + v_loc) psi + alpha E_x[psi].
+
+        With want_grad, returns (E, dE/dpsi, dE/da)."""
+        c = self.cells[cell]
+        self._check(psi, cell, c["nb"], "psi")
+        av = (C.c_double * 3)(*[float(x) for x in a_over_c])
+        e = C.c_double()
+        g = torch.empty_like(psi) if want_grad else None
+        ga = (C.c_double * 3)()
+        N.check(self._lib.taylor_energy(self._h, cell, _ptr(psi), _ptr(vloc) if vloc is not None else None, av,
+                                        float(alpha), C.byref(e), _ptr(g), ga if want_grad else None, _stream()))
+        return (e.value, g, np.array([ga[0], ga[1], ga[2]])) if want_grad else e.value
+
     def orthonormalize(self, psi, cell=0):
         c = self.cells[cell]
         self._check(psi, cell, c["nb"], "psi")

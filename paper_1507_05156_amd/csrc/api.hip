@@ -74,14 +74,6 @@ fock_status Plan::check_ready(int cell) const {
 }
 
 // ------------------------------------------------------------------ plumbing
-static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
-
-static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-  const char* x = (const char*)a;
-  const char* y = (const char*)b;
-  return x < y + nb && y < x + na;
-}
-
 fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
                             double scale, bool accumulate, hipStream_t st) {
   const int nr = c.nr;

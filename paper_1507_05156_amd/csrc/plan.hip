@@ -97,6 +97,10 @@ fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
   if ((e = hipMemcpy(c.qzero.ptr, qz.data(), qz.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "upload q flags");
 
+  if ((s = c.kvec.ensure(c.kpts.size() * sizeof(double), 0, "k-points")) != FOCK_OK) return s;
+  if ((e = hipMemcpy(c.kvec.ptr, c.kpts.data(), c.kpts.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_fail(e, "upload k-points");
   if ((s = c.K64.ensure((size_t)c.nq * c.nr * sizeof(double), 0, "FP64 kernel tables")) != FOCK_OK) return s;
   if ((e = launch_build_table_f64((double*)c.K64.ptr, (const double*)c.qvec.ptr, (const int*)c.qzero.ptr, c.nq,
                                   c.geom, c.omega, 1.0 / c.nr, 0)) != hipSuccess)
@@ -156,8 +160,11 @@ void Plan::destroy() {
     c.qzero.release();
     c.K64.release();
     c.Kt.release();
+    c.kvec.release();
   }
-  for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres}) b->release();
+  for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &psi0, &phiA,
+                    &phiB, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms, &red6, &vloc_buf})
+    b->release();
   if (host_pinned) (void)hipHostFree(host_pinned);
   host_pinned = nullptr;
   magic = 0;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,13 @@ struct DevBuf {
   void release();
 };
 
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
 struct Cell {
   Geom geom{};
   int nr = 0, nk = 0, nb = 0;
@@ -32,6 +40,7 @@ struct Cell {
   DevBuf qidx, qvec, qzero;   // int[nk*nk], double[nq*3], int[nq]
   DevBuf K64;                 // double[nq][nr], 1/N_r folded, natural slot order
   DevBuf Kt;                  // float[nq][nr], fused-kernel layout (FP32 plans)
+  DevBuf kvec;                // double[nk][3] k-points on the device
 };
 
 struct Plan {
@@ -45,6 +54,8 @@ struct Plan {
   size_t batch_cap = size_t(1) << 30;       // plain path: bytes per pair batch
   int xcd_map = 1;
   DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres;
+  DevBuf psi0, phiA, phiB, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
+  std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -68,6 +79,12 @@ struct Plan {
                      const c64** out);
   // sum conj(a) b over count elements in FP64 (fixed order); synchronises st
   fock_status dot(const c128* a, const c128* b, size_t count, hipStream_t st, double* re, double* im);
+
+  // propagator pieces (prop_api.hip)
+  fock_status kinetic(Cell& c, const c128* x, int nf, c128* y, const double a[3], hipStream_t st);
+  fock_status h_apply(Cell& c, const c128* u, const c128* x, c128* out, const c128* base, double cre, double cim,
+                      const double* vloc, const double a[3], double alpha, hipStream_t st);
+  fock_status field_bufs(Cell& c, std::initializer_list<DevBuf*> bufs, int nfields_per_k);
 };
 
 }  // namespace fockmi

@@ -1,0 +1,268 @@
+// Taylor propagation (Eqs. (9)-(10)), its reverse mode, the energy functional
+// (Eq. (22) restricted to kinetic + local + Fock-like pieces) and FP64
+// orthonormalisation, on top of the exchange operator of api.hip.
+//
+// One step: psi <- sum_{m=0}^{M} phi_m, phi_0 = psi(t_n),
+//           phi_m = (-i dt / m) h phi_{m-1},
+//           h = T[a] + v_loc + alpha V_x[psi(t_n)]   (h(t + dt/2) ~ h(t_n), V_x frozen)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "../../include/fockmi.h"
+#include "plan.hpp"
+#include "prop.hpp"
+
+using namespace fockmi;
+
+namespace fockmi {
+
+extern thread_local std::string g_last_error;
+
+fock_status Plan::field_bufs(Cell& c, std::initializer_list<DevBuf*> bufs, int nf) {
+  const size_t bytes = (size_t)c.nk * nf * c.nr * sizeof(c128);
+  for (DevBuf* b : bufs) {
+    fock_status s = b->ensure(bytes, workspace_cap, "propagator work array");
+    if (s != FOCK_OK) return s;
+  }
+  return FOCK_OK;
+}
+
+// y = T[a] x (FFT, multiply by |k+G+a|^2/2 / N_r, inverse FFT), x and y distinct
+fock_status Plan::kinetic(Cell& c, const c128* x, int nf, c128* y, const double a[3], hipStream_t st) {
+  const size_t bytes = (size_t)c.nk * nf * c.nr * sizeof(c128);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(y, x, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "kinetic copy");
+  if ((e = launch_fft3_plain(y, c.nk * nf, c.geom, -1, st)) != hipSuccess) return hip_fail(e, "kinetic FFT");
+  if ((e = launch_kinetic_mul(y, (const double*)c.kvec.ptr, c.nk, nf, c.geom, a, 1.0 / c.nr, st)) != hipSuccess)
+    return hip_fail(e, "kinetic multiply");
+  if ((e = launch_fft3_plain(y, c.nk * nf, c.geom, +1, st)) != hipSuccess) return hip_fail(e, "kinetic inverse FFT");
+  return FOCK_OK;
+}
+
+// out = (base ? base : 0) + (cre + i cim) * h x, with h = T[a] + v_loc + alpha V_x[u]; out distinct from x
+fock_status Plan::h_apply(Cell& c, const c128* u, const c128* x, c128* out, const c128* base, double cre, double cim,
+                          const double* vloc, const double a[3], double alpha, hipStream_t st) {
+  fock_status s;
+  if ((s = field_bufs(c, {&kin}, c.nb)) != FOCK_OK) return s;
+  if ((s = kinetic(c, x, c.nb, (c128*)kin.ptr, a, st)) != FOCK_OK) return s;
+  const c128* vx = nullptr;
+  if (alpha != 0.0) {
+    if ((s = field_bufs(c, {&vxb}, c.nb)) != FOCK_OK) return s;
+    if ((s = general(c, x, c.nb, u, u, c.nb, (c128*)vxb.ptr, -1.0 / c.nk, false, st)) != FOCK_OK) return s;
+    vx = (const c128*)vxb.ptr;
+  }
+  const long count = (long)c.nk * c.nb * c.nr;
+  hipError_t e = launch_hcombine(out, base, (const c128*)kin.ptr, x, vx, vloc, alpha, cre, cim, count, c.nr, st);
+  if (e != hipSuccess) return hip_fail(e, "h combine");
+  return FOCK_OK;
+}
+
+}  // namespace fockmi
+
+namespace {
+
+fock_status common_checks(fockmi_plan plan, int cell, Plan** pp) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = p->check_ready(cell);
+  if (s != FOCK_OK) return s;
+  *pp = p;
+  return FOCK_OK;
+}
+
+fock_status check_step_args(const Cell& c, double dt, int order, const double* A_over_c) {
+  if (!A_over_c) return fail(FOCK_ERR_ARG, "A_over_c is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(A_over_c[d])) return fail(FOCK_ERR_ARG, "A_over_c is not finite");
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(FOCK_ERR_ARG, "dt must be > 0");
+  if (order < 1 || order > 4) return fail(FOCK_ERR_ARG, "order must be in 1..4 (got %d)", order);
+  (void)c;
+  return FOCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fock_status taylor_step(fockmi_plan plan, int cell, void* psi, const double* vloc, const double A_over_c[3],
+                        double dt, double alpha, int order, double* max_norm_dev, void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!psi) return fail(FOCK_ERR_ARG, "psi is NULL");
+  if (!aligned16(psi) || (vloc && ((uintptr_t)vloc & 7u))) return fail(FOCK_ERR_ARG, "misaligned pointer");
+  if ((s = check_step_args(c, dt, order, A_over_c)) != FOCK_OK) return s;
+  if (!std::isfinite(alpha)) return fail(FOCK_ERR_ARG, "alpha is not finite");
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = p->field_bufs(c, {&p->psi0, &p->phiA, &p->phiB}, c.nb)) != FOCK_OK) return s;
+  const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  const long count = (long)c.nk * c.nb * c.nr;
+  c128* P = (c128*)psi;
+  c128* psi0 = (c128*)p->psi0.ptr;
+  c128* cur = (c128*)p->phiA.ptr;
+  c128* nxt = (c128*)p->phiB.ptr;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(psi0, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
+  if ((e = hipMemcpyAsync(cur, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
+  for (int m = 1; m <= order; ++m) {
+    // phi_m = (-i dt/m) h phi_{m-1}
+    if ((s = p->h_apply(c, psi0, cur, nxt, nullptr, 0.0, -dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+    if ((e = launch_scale_add(P, nxt, 1.0, 0.0, count, st)) != hipSuccess) return hip_fail(e, "accumulate step");
+    std::swap(cur, nxt);
+  }
+  if (!max_norm_dev) return FOCK_OK;
+  const int nf = c.nk * c.nb;
+  if ((s = p->norms.ensure(nf * sizeof(double), 0, "norms")) != FOCK_OK) return s;
+  if ((e = launch_norms((double*)p->norms.ptr, P, nf, c.nr, st)) != hipSuccess) return hip_fail(e, "norms");
+  p->host_norms.resize(nf);
+  if ((e = hipMemcpyAsync(p->host_norms.data(), p->norms.ptr, nf * sizeof(double), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return hip_fail(e, "norm copy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "norm sync");
+  double dev = 0.0;
+  const double w = c.vol / c.nr;
+  for (double n2 : p->host_norms) dev = std::max(dev, std::fabs(w * n2 - 1.0));
+  *max_norm_dev = dev;
+  return dev > 1e-6 ? FOCK_WARN_NORM : FOCK_OK;
+}
+
+fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const double* vloc,
+                            const double A_over_c[3], double dt, double alpha, int order, const void* g_next,
+                            void* g_psi, double g_a[3], void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!psi_n || !g_next || !g_psi || !g_a) return fail(FOCK_ERR_ARG, "NULL pointer");
+  if (!aligned16(psi_n) || !aligned16(g_next) || !aligned16(g_psi)) return fail(FOCK_ERR_ARG, "misaligned pointer");
+  if ((s = check_step_args(c, dt, order, A_over_c)) != FOCK_OK) return s;
+  const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  if (overlap(g_psi, bytes, psi_n, bytes) || overlap(g_psi, bytes, g_next, bytes))
+    return fail(FOCK_ERR_ARG, "g_psi overlaps an input");
+  hipStream_t st = (hipStream_t)stream;
+  const long count = (long)c.nk * c.nb * c.nr;
+  // forward recomputation: phi_0 .. phi_{M-1}
+  if ((s = p->phis.ensure(bytes * order, p->workspace_cap, "stored Taylor terms")) != FOCK_OK) return s;
+  if ((s = p->field_bufs(c, {&p->lam, &p->lam2, &p->gtmp, &p->ftmp}, c.nb)) != FOCK_OK) return s;
+  c128* phis = (c128*)p->phis.ptr;
+  const c128* U = (const c128*)psi_n;
+  const c128* G = (const c128*)g_next;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(phis, U, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy");
+  for (int m = 1; m < order; ++m) {
+    if ((s = p->h_apply(c, U, phis + (size_t)(m - 1) * count, phis + (size_t)m * count, nullptr, 0.0, -dt / m, vloc,
+                        A_over_c, alpha, st)) != FOCK_OK)
+      return s;
+  }
+  c128* lam = (c128*)p->lam.ptr;
+  c128* lam2 = (c128*)p->lam2.ptr;
+  c128* gt = (c128*)p->gtmp.ptr;
+  c128* ft = (c128*)p->ftmp.ptr;
+  c128* GP = (c128*)g_psi;
+  if ((e = hipMemcpyAsync(lam, G, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy");
+  if ((e = hipMemsetAsync(GP, 0, bytes, st)) != hipSuccess) return hip_fail(e, "zero g_psi");
+  const int nblk = 512;
+  if ((s = p->partial.ensure(6 * nblk * sizeof(double), 0, "reduction partials")) != FOCK_OK) return s;
+  if ((s = p->red6.ensure(6 * sizeof(double) * order, 0, "reduction results")) != FOCK_OK) return s;
+  for (int m = order; m >= 1; --m) {
+    const c128* phim1 = phis + (size_t)(m - 1) * count;
+    // c_m = -i dt/m ; conj(c_m) = +i dt/m
+    // d L / d a: Re[c_m / N_r sum conj(DFT lam_m) (k+G+a) DFT phi_{m-1}]
+    if ((e = hipMemcpyAsync(gt, lam, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy");
+    if ((e = hipMemcpyAsync(ft, phim1, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy");
+    if ((e = launch_fft3_plain(gt, c.nk * c.nb, c.geom, -1, st)) != hipSuccess) return hip_fail(e, "FFT");
+    if ((e = launch_fft3_plain(ft, c.nk * c.nb, c.geom, -1, st)) != hipSuccess) return hip_fail(e, "FFT");
+    if ((e = launch_agrad((double*)p->red6.ptr + 6 * (m - 1), (double*)p->partial.ptr, nblk, gt, ft,
+                          (const double*)c.kvec.ptr, c.nb, c.geom, A_over_c, count, st)) != hipSuccess)
+      return hip_fail(e, "A gradient");
+    if (alpha != 0.0) {
+      // cotangent of V_x[u] phi_{m-1} is conj(c_m) alpha lam_m
+      if ((e = hipMemsetAsync(gt, 0, bytes, st)) != hipSuccess) return hip_fail(e, "zero");
+      if ((e = launch_scale_add(gt, lam, 0.0, alpha * dt / m, count, st)) != hipSuccess) return hip_fail(e, "scale");
+      if ((s = p->general(c, U, c.nb, phim1, gt, c.nb, GP, -1.0 / c.nk, true, st)) != FOCK_OK) return s;
+      if ((s = p->general(c, U, c.nb, gt, phim1, c.nb, GP, -1.0 / c.nk, true, st)) != FOCK_OK) return s;
+    }
+    // lam_{m-1} = g + conj(c_m) h lam_m
+    if ((s = p->h_apply(c, U, lam, lam2, G, 0.0, dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+    std::swap(lam, lam2);
+  }
+  if ((e = launch_scale_add(GP, lam, 1.0, 0.0, count, st)) != hipSuccess) return hip_fail(e, "accumulate");
+  std::vector<double> red(6 * order);
+  if ((e = hipMemcpyAsync(red.data(), p->red6.ptr, red.size() * sizeof(double), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return hip_fail(e, "copy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync");
+  for (int d = 0; d < 3; ++d) g_a[d] = 0.0;
+  for (int m = 1; m <= order; ++m) {
+    // Re[(-i dt/m)(re + i im)] / N_r = (dt/m) im / N_r
+    for (int d = 0; d < 3; ++d) g_a[d] += (dt / m) * red[6 * (m - 1) + 2 * d + 1] / c.nr;
+  }
+  return FOCK_OK;
+}
+
+fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
+                          double alpha, double* e_out, void* grad_psi, double grad_a[3], void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!psi || !A_over_c || !e_out) return fail(FOCK_ERR_ARG, "NULL pointer");
+  if (!aligned16(psi) || (grad_psi && !aligned16(grad_psi))) return fail(FOCK_ERR_ARG, "misaligned pointer");
+  const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  if (grad_psi && overlap(grad_psi, bytes, psi, bytes)) return fail(FOCK_ERR_ARG, "grad_psi overlaps psi");
+  hipStream_t st = (hipStream_t)stream;
+  const long count = (long)c.nk * c.nb * c.nr;
+  if ((s = p->field_bufs(c, {&p->lam}, c.nb)) != FOCK_OK) return s;
+  c128* hpsi = (c128*)p->lam.ptr;
+  const c128* P = (const c128*)psi;
+  if ((s = p->h_apply(c, P, P, hpsi, nullptr, 1.0, 0.0, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+  double hre, him, xre = 0.0, xim = 0.0;
+  if ((s = p->dot(P, hpsi, count, st, &hre, &him)) != FOCK_OK) return s;
+  if (alpha != 0.0 && (s = p->dot(P, (const c128*)p->vxb.ptr, count, st, &xre, &xim)) != FOCK_OK) return s;
+  const double w = c.gs / c.nk * c.vol / c.nr;
+  // sum conj(psi) h psi counts V_x with alpha; the energy counts it with alpha / 2
+  *e_out = w * (hre - 0.5 * alpha * xre);
+  hipError_t e;
+  if (grad_psi) {
+    if ((e = hipMemsetAsync(grad_psi, 0, bytes, st)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = launch_scale_add((c128*)grad_psi, hpsi, 2.0 * w, 0.0, count, st)) != hipSuccess)
+      return hip_fail(e, "gradient");
+  }
+  if (grad_a) {
+    const int nblk = 512;
+    if ((s = p->field_bufs(c, {&p->gtmp}, c.nb)) != FOCK_OK) return s;
+    if ((s = p->partial.ensure(6 * nblk * sizeof(double), 0, "reduction partials")) != FOCK_OK) return s;
+    if ((s = p->red6.ensure(6 * sizeof(double), 0, "reduction results")) != FOCK_OK) return s;
+    c128* F = (c128*)p->gtmp.ptr;
+    if ((e = hipMemcpyAsync(F, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy");
+    if ((e = launch_fft3_plain(F, c.nk * c.nb, c.geom, -1, st)) != hipSuccess) return hip_fail(e, "FFT");
+    if ((e = launch_agrad((double*)p->red6.ptr, (double*)p->partial.ptr, nblk, F, F, (const double*)c.kvec.ptr, c.nb,
+                          c.geom, A_over_c, count, st)) != hipSuccess)
+      return hip_fail(e, "A gradient");
+    double red[6];
+    if ((e = hipMemcpyAsync(red, p->red6.ptr, sizeof(red), hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(e, "copy");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync");
+    for (int d = 0; d < 3; ++d) grad_a[d] = w * red[2 * d] / c.nr;
+  }
+  return FOCK_OK;
+}
+
+fock_status fock_orthonormalize(fockmi_plan plan, int cell, void* psi, void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!psi) return fail(FOCK_ERR_ARG, "psi is NULL");
+  if (!aligned16(psi)) return fail(FOCK_ERR_ARG, "misaligned pointer");
+  hipError_t e = launch_mgs((c128*)psi, c.nk, c.nb, c.nr, c.vol / c.nr, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "Gram-Schmidt");
+  return FOCK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+"""Parity of the propagator, its adjoint, the energy functional, orthonormalisation
+and the autograd wrappers (through the C ABI) with the FP64 oracle.
+
+Independent routes: the oracle's matrix-free Taylor step (pinned against dense
+matrices), its forward-mode (tangent-linear) derivative for a dot-product test
+of the reverse mode, and central finite differences of the GPU path itself.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import taylor as otaylor
+from paper_1507_05156_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+OMEGA = synth.OMEGA_HSE
+TOL = {"fp64": 1e-10, "fp32": 1e-6}
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def setup(n=16, nb=2, seed=400):
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(n, cell, kp, nb, seed=seed)
+    vloc = np.random.default_rng(seed + 1).standard_normal((n, n, n)) * 0.05
+    return cell, kp, u, vloc
+
+
+def plan_for(cell, kp, nb, n, prec):
+    from paper_1507_05156_amd.api import Plan
+    return Plan(dict(n=n, a=cell, kpts=kp, nb=nb, omega=OMEGA), prec=prec)
+
+
+def rel(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_taylor_step_matches_oracle(device, prec):
+    print(f"[gpu] taylor step prec={prec}", flush=True)
+    cell, kp, u, vloc = setup()
+    avec = np.array([0.01, -0.02, 0.03])
+    dt, alpha = 0.02, 0.25
+    ref = otaylor.step_matfree(u, kp, cell, OMEGA, avec, dt, alpha, vloc)
+    plan = plan_for(cell, kp, 2, 16, prec)
+    psi = to_dev(u)
+    dev = plan.taylor_step(psi, avec, dt, alpha, vloc=to_dev(vloc))
+    got = psi.cpu().numpy()
+    assert rel(got, ref) < TOL[prec]
+    nr = 16 ** 3
+    w = oracle.volume(cell) / nr
+    ref_dev = np.max(np.abs(w * np.sum(np.abs(ref) ** 2, axis=(2, 3, 4)) - 1.0))
+    assert abs(dev - ref_dev) < 1e-12 + 1e-6 * ref_dev
+
+
+def test_taylor_step_free_particle_norm(device):
+    """alpha = 0, no local potential: plane-wave diagonal; the FP64 norm drift matches
+    the closed-form amplification 1 - x^6/72 + x^8/576 of each plane-wave component."""
+    print("[gpu] taylor free particle", flush=True)
+    cell = synth.cubic_cell()
+    kp = np.array([[0.1, 0.0, -0.05]])
+    n = 16
+    B = oracle.reciprocal(cell)
+    G = oracle.gvectors((n, n, n), B)
+    r = oracle.grid_points((n, n, n), cell)
+    l = (3, 1, 2)
+    psi = (np.exp(1j * (r @ G[l])) / np.sqrt(oracle.volume(cell)))[None, None]
+    dt = 0.5
+    plan = plan_for(cell, kp, 1, n, "fp64")
+    d = to_dev(psi)
+    dev = plan.taylor_step(d, [0.0, 0.0, 0.0], dt, 0.0)
+    eps = 0.5 * np.sum((kp[0] + G[l]) ** 2)
+    x = eps * dt
+    amp = 1 - x ** 6 / 72 + x ** 8 / 576
+    assert abs(dev - abs(amp - 1.0)) < 1e-12
+    z = -1j * x
+    t4 = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    assert np.max(np.abs(d.cpu().numpy() - t4 * psi)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_taylor_vjp_dot_product_with_oracle_tangent(device, prec):
+    """<g, J d> from the oracle's forward mode equals <J^T g, d> from the GPU reverse mode."""
+    print(f"[gpu] taylor vjp prec={prec}", flush=True)
+    cell, kp, u, vloc = setup(seed=410)
+    avec = np.array([0.01, -0.02, 0.03])
+    dt, alpha = 0.02, 0.25
+    dpsi = synth.random_fields(u.shape, seed=411)
+    dpsi *= np.linalg.norm(u) / np.linalg.norm(dpsi)
+    da = np.array([0.2, -0.5, 0.7])
+    g = synth.random_fields(u.shape, seed=412)
+    Jd = otaylor.step_tangent_matfree(u, dpsi, da, kp, cell, OMEGA, avec, dt, alpha, vloc)
+    lhs = np.real(np.sum(np.conj(g) * Jd))
+    plan = plan_for(cell, kp, 2, 16, prec)
+    gpsi, ga = plan.taylor_step_vjp(to_dev(u), avec, dt, alpha, to_dev(g), vloc=to_dev(vloc))
+    rhs = np.real(np.sum(np.conj(gpsi.cpu().numpy()) * dpsi)) + float(ga @ da)
+    assert abs(lhs - rhs) / abs(lhs) < TOL[prec]
+
+
+def test_taylor_vjp_matches_gpu_finite_difference(device):
+    """Central differences (h = 1e-5, direction scaled to |d| = |psi|) of the GPU step itself."""
+    print("[gpu] taylor vjp fd", flush=True)
+    cell, kp, u, vloc = setup(seed=420)
+    avec = np.array([0.0, 0.0, 0.02])
+    dt, alpha = 0.02, 0.25
+    plan = plan_for(cell, kp, 2, 16, "fp64")
+    g = synth.random_fields(u.shape, seed=421)
+    d = synth.random_fields(u.shape, seed=422)
+    d *= np.linalg.norm(u) / np.linalg.norm(d)
+    da = np.array([0.0, 0.0, 1.0])
+    h = 1e-5
+
+    def L(x, av):
+        t = to_dev(x)
+        plan.taylor_step(t, av, dt, alpha, vloc=to_dev(vloc), want_norm=False)
+        return np.real(np.sum(np.conj(g) * t.cpu().numpy()))
+
+    fd = (L(u + h * d, avec + h * da) - L(u - h * d, avec - h * da)) / (2 * h)
+    gpsi, ga = plan.taylor_step_vjp(to_dev(u), avec, dt, alpha, to_dev(g), vloc=to_dev(vloc))
+    ad = np.real(np.sum(np.conj(gpsi.cpu().numpy()) * d)) + float(ga @ da)
+    assert abs(fd - ad) / abs(ad) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_energy_functional_matches_oracle(device, prec):
+    print(f"[gpu] energy functional prec={prec}", flush=True)
+    cell, kp, u, vloc = setup(seed=430)
+    avec = np.array([0.01, -0.02, 0.03])
+    e_ref, g_ref, ga_ref = otaylor.energy_matfree(u, kp, cell, OMEGA, avec, 0.25, vloc)
+    plan = plan_for(cell, kp, 2, 16, prec)
+    e, g, ga = plan.energy_functional(to_dev(u), avec, 0.25, vloc=to_dev(vloc), want_grad=True)
+    assert abs(e - e_ref) / abs(e_ref) < TOL[prec]
+    assert rel(g.cpu().numpy(), g_ref) < TOL[prec]
+    assert np.max(np.abs(ga - ga_ref)) < TOL[prec] * np.max(np.abs(ga_ref)) + 1e-14
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_orthonormalize_matches_oracle(device, n):
+    print(f"[gpu] orthonormalize n={n}", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(n, cell, kp, 5, seed=440 + n, orthonormal=False)
+    ref = oracle.gram_schmidt(u, cell)
+    plan = plan_for(cell, kp, 5, n, "fp64")
+    d = to_dev(u)
+    plan.orthonormalize(d)
+    assert rel(d.cpu().numpy(), ref) < 1e-12
+
+
+def test_autograd_energy_and_apply(device):
+    """FockEnergy / FockApply backward against the oracle's closed forms."""
+    print("[gpu] autograd apply/energy", flush=True)
+    import torch
+    from paper_1507_05156_amd import autograd as ag
+    cell, kp, u, _ = setup(seed=450)
+    plan = plan_for(cell, kp, 2, 16, "fp64")
+    ud = to_dev(u).requires_grad_(True)
+    e = ag.fock_energy(ud, plan)
+    e.backward()
+    assert rel(ud.grad.cpu().numpy(), oracle.energy_grad(u, kp, cell, OMEGA)) < 1e-10
+    phi = synth.random_fields(u.shape, seed=451)
+    g = synth.random_fields(u.shape, seed=452)
+    ud = to_dev(u).requires_grad_(True)
+    pd = to_dev(phi).requires_grad_(True)
+    y = ag.fock_apply(ud, pd, plan)
+    y.backward(to_dev(g))
+    gu_ref, gp_ref = oracle.fock_vjp(u, phi, g, kp, cell, OMEGA)
+    assert rel(ud.grad.cpu().numpy(), gu_ref) < 1e-10
+    assert rel(pd.grad.cpu().numpy(), gp_ref) < 1e-10
+
+
+def test_autograd_propagation_a0_gradient(device):
+    """dE_ex/dA0 through checkpointed Taylor steps: adjoint vs central FD (h = 1e-5) vs the
+    oracle's forward-mode propagation."""
+    print("[gpu] autograd propagate", flush=True)
+    import torch
+    from paper_1507_05156_amd import autograd as ag
+    cell, kp, u, _ = setup(seed=460)
+    plan = plan_for(cell, kp, 2, 16, "fp64")
+    kw = dict(nsteps=4, dt=0.05, alpha=0.25, omega_l=0.0569614, checkpoint_every=2)
+    A0 = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    _, eex = ag.propagate(plan, to_dev(u), A0, **kw)
+    eex.backward()
+    ad = float(A0.grad)
+    h = 1e-5
+    with torch.no_grad():
+        ep = float(ag.propagate(plan, to_dev(u), torch.tensor(0.05 + h, dtype=torch.float64), **kw)[1])
+        em = float(ag.propagate(plan, to_dev(u), torch.tensor(0.05 - h, dtype=torch.float64), **kw)[1])
+    fd = (ep - em) / (2 * h)
+    assert abs(fd - ad) / abs(ad) < 1e-6
+    # oracle forward mode, matrix-free, same pulse and steps
+    Td = kw["nsteps"] * kw["dt"]
+    psi = u.copy()
+    dpsi = np.zeros_like(u)
+    for s in range(kw["nsteps"]):
+        t = s * kw["dt"]
+        av = otaylor.pulse_a_over_c(t, 0.05, kw["omega_l"], Td)
+        dav = otaylor.pulse_a_over_c(t, 1.0, kw["omega_l"], Td)
+        dpsi = otaylor.step_tangent_matfree(psi, dpsi, dav, kp, cell, OMEGA, av, kw["dt"], kw["alpha"])
+        psi = otaylor.step_matfree(psi, kp, cell, OMEGA, av, kw["dt"], kw["alpha"])
+    _, gE, _ = otaylor.energy_matfree(psi, kp, cell, OMEGA, np.zeros(3), kw["alpha"])
+    tl = np.real(np.sum(np.conj(gE) * dpsi))
+    assert abs(tl - ad) / abs(tl) < 1e-9

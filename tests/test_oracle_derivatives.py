@@ -157,3 +157,51 @@ def test_gram_schmidt_is_qr_with_positive_diagonal():
         assert np.max(np.abs(out[k] - ref)) < 1e-12 * np.max(np.abs(ref))
         S = w * out[k].reshape(4, -1).conj() @ out[k].reshape(4, -1).T
         assert np.max(np.abs(S - np.eye(4))) < 1e-13
+
+
+def test_matrix_free_step_matches_dense():
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(4, cell, kp, 2, seed=40, ecut=20.0)
+    vloc = np.random.default_rng(41).standard_normal((4, 4, 4)) * 0.1
+    avec = np.array([0.01, -0.02, 0.03])
+    dense = otaylor.step(u, kp, cell, OMEGA, avec, 0.05, 0.25, vloc)
+    mf = otaylor.step_matfree(u, kp, cell, OMEGA, avec, 0.05, 0.25, vloc)
+    assert np.max(np.abs(dense - mf)) < 1e-13
+
+
+def test_matrix_free_tangent_matches_fd():
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(4, cell, kp, 2, seed=42, ecut=20.0)
+    du = synth.random_fields(u.shape, seed=43)
+    du *= np.linalg.norm(u) / np.linalg.norm(du)
+    da = np.array([0.3, -0.2, 0.5])
+    avec = np.array([0.01, -0.02, 0.03])
+    args = dict(kpts=kp, a=cell, omega=OMEGA, dt=0.05, alpha=0.25)
+    h = 1e-5
+    fp = otaylor.step_matfree(u + h * du, avec=avec + h * da, **args)
+    fm = otaylor.step_matfree(u - h * du, avec=avec - h * da, **args)
+    fd = (fp - fm) / (2 * h)
+    tl = otaylor.step_tangent_matfree(u, du, da, avec=avec, **args)
+    assert np.linalg.norm(fd - tl) / np.linalg.norm(tl) < 1e-8
+
+
+def test_energy_matfree_matches_dense_and_fd():
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(4, cell, kp, 2, seed=44, ecut=20.0)
+    avec = np.array([0.01, -0.02, 0.03])
+    e, g, ga = otaylor.energy_matfree(u, kp, cell, OMEGA, avec, 0.25)
+    assert abs(e - otaylor.energy(u, kp, cell, OMEGA, avec, 0.25).real) < 1e-13 * abs(e)
+    d = synth.random_fields(u.shape, seed=45)
+    d *= np.linalg.norm(u) / np.linalg.norm(d)
+    h = 1e-5
+    f = lambda x, av: otaylor.energy_matfree(x, kp, cell, OMEGA, av, 0.25)[0]
+    fd = (f(u + h * d, avec) - f(u - h * d, avec)) / (2 * h)
+    assert abs(fd - redot(g, d)) < 1e-8 * abs(fd)
+    for ax in range(3):
+        da = np.zeros(3)
+        da[ax] = 1.0
+        fd = (f(u, avec + h * da) - f(u, avec - h * da)) / (2 * h)
+        assert abs(fd - ga[ax]) < 1e-7 * max(1.0, abs(fd))
