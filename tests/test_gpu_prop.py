@@ -56,7 +56,8 @@ def test_taylor_step_matches_oracle(device, prec):
     nr = 16 ** 3
     w = oracle.volume(cell) / nr
     ref_dev = np.max(np.abs(w * np.sum(np.abs(ref) ** 2, axis=(2, 3, 4)) - 1.0))
-    assert abs(dev - ref_dev) < 1e-12 + 1e-6 * ref_dev
+    # the FP32 form changes psi at the 1e-10 level (alpha dt times its 1e-7 operator error)
+    assert abs(dev - ref_dev) < (1e-12 if prec == "fp64" else 1e-9)
 
 
 def test_taylor_step_free_particle_norm(device):
