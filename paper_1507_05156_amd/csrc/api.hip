@@ -16,6 +16,7 @@
 #include <string>
 #include <tuple>
 #include <vector>
+#include <cstdlib>
 
 #include "../../include/fockmi.h"
 #include "kernels.hpp"
@@ -74,19 +75,58 @@ fock_status Plan::check_ready(int cell) const {
 }
 
 // ------------------------------------------------------------------ plumbing
+static fock_status plain_pipeline(Plan& pl, Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                                  c128* out, double scale, bool accumulate, hipStream_t st, size_t cap);
+
 fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
                             double scale, bool accumulate, hipStream_t st) {
+  const std::string key = key_for(c, nx, "plain");
+  TuneEntry te;
+  if (tune.get(key, &te)) return plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, accumulate, st,
+                                                (size_t)te.fields["batch_mb"] << 20);
+  if (!tuning || accumulate) return plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, accumulate, st, batch_cap);
+  // measure the pair-batch size (each candidate writes the same result)
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tuning event");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
+  double best = 1e300;
+  int bmb = 1024;
+  for (int mb : {256, 1024}) {
+    (void)hipEventRecord(e0, st);
+    fock_status s = plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, false, st, (size_t)mb << 20);
+    if (s != FOCK_OK) return s;
+    (void)hipEventRecord(e1, st);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      bmb = mb;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  te.fields["batch_mb"] = bmb;
+  te.fields["ms"] = best;
+  tune.put(key, te);
+  save_tune();
+  return plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, false, st, (size_t)bmb << 20);
+}
+
+static fock_status plain_pipeline(Plan& pl, Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                                  c128* out, double scale, bool accumulate, hipStream_t st, size_t cap) {
   const int nr = c.nr;
   const size_t per_k = (size_t)ns * nx * nr * sizeof(c128);
-  int kb = (int)std::max<size_t>(1, batch_cap / std::max<size_t>(per_k, 1));
+  int kb = (int)std::max<size_t>(1, cap / std::max<size_t>(per_k, 1));
   kb = std::min(kb, c.nk);
   kb = std::max(1, std::min(kb, 65535 / std::max(1, ns * nx)));  // grid.y of the batch kernels
   if ((long)ns * nx > 65535) return fail(FOCK_ERR_SIZE, "too many band pairs per k-point pair (%d x %d)", ns, nx);
-  fock_status s = batch.ensure((size_t)kb * per_k, workspace_cap, "plain-path batch buffer");
+  fock_status s = pl.batch.ensure((size_t)kb * per_k, pl.workspace_cap, "plain-path batch buffer");
   if (s != FOCK_OK) return s;
-  c128* buf = (c128*)batch.ptr;
+  c128* buf = (c128*)pl.batch.ptr;
   hipError_t e;
-  if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
+  if ((e = pl.prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
   for (int k = 0; k < c.nk; ++k) {
     const c128* Xk = X + (size_t)k * nx * nr;
     c128* outk = out + (size_t)k * nx * nr;
@@ -106,7 +146,7 @@ fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const
         return hip_fail(e, "accumulate");
     }
   }
-  if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
+  if ((e = pl.prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
   return FOCK_OK;
 }
 
@@ -161,11 +201,63 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
   a.scale = scale;
   a.accumulate = accumulate ? 1 : 0;
   a.xcd_map = xcd_map;
-  hipError_t e = prof_begin(st);
-  if (e != hipSuccess) return hip_fail(e, "profile event");
-  if ((e = launch_fused_apply(c.geom.n1, a, st)) != hipSuccess) return hip_fail(e, "fused pair kernel");
+  a.n = c.geom.n1;
+  int variant = 0;
+  hipError_t e;
+  const std::string key = key_for(c, nx, "fused");
+  TuneEntry te;
+  if (tune.get(key, &te)) {
+    variant = (int)te.fields["variant"];
+    a.xcd_map = (int)te.fields["xcd_map"];
+    if (variant >= fused_variants(c.geom.n1)) variant = 0;
+  } else if (tuning && !accumulate) {
+    // measure every candidate on this call's data (each writes the same result)
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tuning event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
+    double best = 1e300;
+    int bv = 0, bx = 1;
+    for (int v = 0; v < fused_variants(c.geom.n1); ++v) {
+      for (int x = 0; x < 2; ++x) {
+        a.xcd_map = x;
+        (void)hipEventRecord(e0, st);
+        if ((e = launch_fused_apply(c.geom.n1, a, st, v)) != hipSuccess) return hip_fail(e, "fused pair kernel");
+        (void)hipEventRecord(e1, st);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          bv = v;
+          bx = x;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    te.fields["variant"] = bv;
+    te.fields["xcd_map"] = bx;
+    te.fields["ms"] = best;
+    tune.put(key, te);
+    save_tune();
+    variant = bv;
+    a.xcd_map = bx;
+  }
+  if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
+  if ((e = launch_fused_apply(c.geom.n1, a, st, variant)) != hipSuccess) return hip_fail(e, "fused pair kernel");
   if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
   return FOCK_OK;
+}
+
+std::string Plan::key_for(const Cell& c, int nx, const char* what) const {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s/%s/%s/n%dx%dx%d/nk%d/nb%d/nx%d", arch_name().c_str(),
+                prec == FOCK_FP32_COMP ? "fp32" : "fp64", what, c.geom.n1, c.geom.n2, c.geom.n3, c.nk, c.nb, nx);
+  return buf;
+}
+
+void Plan::save_tune() {
+  if (!tune_path.empty()) (void)tune.save(tune_path);
 }
 
 fock_status Plan::general(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
@@ -208,7 +300,16 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
     delete p;
     return fail(FOCK_ERR_HIP, "hipGetDevice failed");
   }
-  if (tune_cache_json) p->tune_path = tune_cache_json;
+  if (tune_cache_json) {
+    p->tune_path = tune_cache_json;
+    p->tuning = true;
+    (void)p->tune.load(p->tune_path);
+  }
+  if (const char* g = std::getenv("FOCKMI_GRAPH")) p->use_graph = std::atoi(g) != 0;
+  {
+    hipDeviceProp_t prop;
+    p->num_cus = hipGetDeviceProperties(&prop, p->device) == hipSuccess ? prop.multiProcessorCount : 256;
+  }
   fock_status s = FOCK_OK;
   for (int ci = 0; ci < ncells && s == FOCK_OK; ++ci) {
     p->cells.emplace_back();

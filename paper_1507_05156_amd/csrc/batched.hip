@@ -1,5 +1,15 @@
-// fock_apply_batched: every cell of an FP32 plan in one call.
+// fock_apply_batched: all cells of a plan in one persistent launch, replayed
+// from a captured hipGraph while the caller passes the same buffers.
+//
+// Per call: one complex64 shadow per orbital array (and per distinct target
+// array), a queue-counter reset (a one-thread kernel, no memset node), and the
+// persistent kernel over the (cell, target) queue ordered by decreasing cost.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
 
 #include "../../include/fockmi.h"
 #include "plan.hpp"
@@ -7,8 +17,176 @@
 using namespace fockmi;
 
 namespace fockmi {
+
 extern thread_local std::string g_last_error;
+
+void BatchState::reset_graph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
+  ready = false;
 }
+
+void BatchState::release() {
+  reset_graph();
+  for (int i = 0; i < kMaxBatchCells; ++i) {
+    shadow_u[i].release();
+    shadow_x[i].release();
+    comp[i].release();
+  }
+  accs.release();
+  queue.release();
+  counter.release();
+  if (cap) (void)hipStreamDestroy(cap);
+  cap = nullptr;
+  key.clear();
+}
+
+// cost of one target of a cell: pairs x nominal flops of one pair
+static double item_cost(const Cell& c) {
+  const double nr = (double)c.nr;
+  return (double)c.nk * c.nb * (10.0 * nr * std::log2(nr) + 16.0 * nr);
+}
+
+fock_status Plan::run_batched(const void* const* u, const void* const* phi, const int* nphi, void* const* vphi,
+                              hipStream_t st) {
+  const int nc = (int)cells.size();
+  BatchState& B = bstate;
+  std::vector<const void*> key;
+  for (int ci = 0; ci < nc; ++ci) {
+    key.push_back(u[ci]);
+    key.push_back(phi[ci]);
+    key.push_back(vphi[ci]);
+    key.push_back((const void*)(intptr_t)nphi[ci]);
+  }
+  hipError_t e;
+  fock_status s;
+  if (!(B.ready && key == B.key)) {
+    B.reset_graph();
+    B.key = key;
+    // buffers (allocated before any capture; their addresses are baked into the graph)
+    int nmax = 0;
+    size_t acc_slots_needed = 0;
+    std::vector<int> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return item_cost(cells[x]) > item_cost(cells[y]); });
+    std::vector<int> q;
+    for (int ci : order) {
+      Cell& c = cells[ci];
+      nmax = std::max(nmax, c.geom.n1);
+      for (int it = 0; it < c.nk * nphi[ci]; ++it) {
+        q.push_back(ci);
+        q.push_back(it);
+      }
+    }
+    B.total = (int)q.size() / 2;
+    B.nthreads = batched_threads(nmax);
+    int mult = 1;
+    {
+      std::string k = arch_name() + "/fp32/batched";
+      for (int ci = 0; ci < nc; ++ci) k += "/" + key_for(cells[ci], nphi[ci], "cell");
+      TuneEntry te;
+      if (tune.get(k, &te)) mult = std::max(1, (int)te.fields["wg_per_cu"]);
+    }
+    B.nwg = num_cus * mult;
+    for (int ci = 0; ci < nc; ++ci) {
+      Cell& c = cells[ci];
+      if (c.geom.n1 == 32) acc_slots_needed = (size_t)B.nwg;
+      const size_t nu = (size_t)c.nk * c.nb * c.nr, nx = (size_t)c.nk * nphi[ci] * c.nr;
+      if ((s = B.shadow_u[ci].ensure(nu * sizeof(c64), workspace_cap, "batched shadow (u)")) != FOCK_OK) return s;
+      if (phi[ci] != u[ci] &&
+          (s = B.shadow_x[ci].ensure(nx * sizeof(c64), workspace_cap, "batched shadow (phi)")) != FOCK_OK)
+        return s;
+      if ((s = B.comp[ci].ensure(nx * sizeof(c128), workspace_cap, "batched compensation")) != FOCK_OK) return s;
+    }
+    if (acc_slots_needed &&
+        (s = B.accs.ensure(fused_acc_scratch_elems(32, (int)acc_slots_needed) * sizeof(c64), workspace_cap,
+                           "batched FP32 sums")) != FOCK_OK)
+      return s;
+    if ((s = B.queue.ensure(q.size() * sizeof(int), 0, "batched queue")) != FOCK_OK) return s;
+    if ((s = B.counter.ensure(sizeof(int), 0, "batched counter")) != FOCK_OK) return s;
+    if ((e = hipMemcpy(B.queue.ptr, q.data(), q.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "upload queue");
+    BatchArgs& A = B.args;
+    A = BatchArgs{};
+    for (int ci = 0; ci < nc; ++ci) {
+      Cell& c = cells[ci];
+      FusedArgs& a = A.cells[ci];
+      a.P = a.M = (const c64*)B.shadow_u[ci].ptr;
+      a.X = phi[ci] == u[ci] ? a.P : (const c64*)B.shadow_x[ci].ptr;
+      a.Kt = (const float*)c.Kt.ptr;
+      a.qidx = (const int*)c.qidx.ptr;
+      a.out = (c128*)vphi[ci];
+      a.comp = (c128*)B.comp[ci].ptr;
+      a.accs = (c64*)B.accs.ptr;
+      a.nk = c.nk;
+      a.nx = nphi[ci];
+      a.nb = c.nb;
+      a.item0 = 0;
+      a.nitems = c.nk * nphi[ci];
+      a.scale = -1.0 / c.nk;
+      a.accumulate = 0;
+      a.xcd_map = 0;
+      a.n = c.geom.n1;
+    }
+    A.queue = (const int*)B.queue.ptr;
+    A.counter = (int*)B.counter.ptr;
+    A.total = B.total;
+    if (!B.cap && (e = hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "capture stream");
+    B.ready = true;
+  }
+
+  auto enqueue = [&](hipStream_t q) -> fock_status {
+    hipError_t ee;
+    for (int ci = 0; ci < nc; ++ci) {
+      Cell& c = cells[ci];
+      const long nu = (long)c.nk * c.nb * c.nr, nx = (long)c.nk * nphi[ci] * c.nr;
+      if ((ee = launch_to_c64((c64*)B.shadow_u[ci].ptr, (const c128*)u[ci], nu, q)) != hipSuccess)
+        return hip_fail(ee, "batched shadow");
+      if (phi[ci] != u[ci] &&
+          (ee = launch_to_c64((c64*)B.shadow_x[ci].ptr, (const c128*)phi[ci], nx, q)) != hipSuccess)
+        return hip_fail(ee, "batched shadow");
+    }
+    if ((ee = launch_fused_batched(B.args, B.nthreads, B.nwg, q)) != hipSuccess)
+      return hip_fail(ee, "persistent kernel");
+    return FOCK_OK;
+  };
+
+  if (!use_graph) {
+    if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
+    if ((s = enqueue(st)) != FOCK_OK) return s;
+    if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
+    return FOCK_OK;
+  }
+  if (!B.exec) {
+    // the capture stream waits for the caller's prior work through the graph
+    // launch itself; capture only records
+    if ((e = hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    s = enqueue(B.cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(B.cap, &g);
+    if (s != FOCK_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    B.graph = g;
+    if ((e = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0)) != hipSuccess) {
+      B.exec = nullptr;
+      return hip_fail(e, "instantiate graph");
+    }
+  }
+  if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
+  if ((e = hipGraphLaunch(B.exec, st)) != hipSuccess) return hip_fail(e, "graph launch");
+  if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
+  return FOCK_OK;
+}
+
+}  // namespace fockmi
 
 extern "C" fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
                                           const int* nphi, void* const* vphi, void* stream) {
@@ -18,15 +196,26 @@ extern "C" fock_status fock_apply_batched(fockmi_plan plan, const void* const* u
   fock_status s = p->check_ready(0);
   if (s != FOCK_OK) return s;
   if (!u_occ || !phi || !nphi || !vphi) return fail(FOCK_ERR_ARG, "NULL pointer array");
-  for (int ci = 0; ci < (int)p->cells.size(); ++ci) {
+  const int nc = (int)p->cells.size();
+  for (int ci = 0; ci < nc; ++ci) {
+    const Cell& c = p->cells[ci];
     if (!u_occ[ci] || !phi[ci] || !vphi[ci]) return fail(FOCK_ERR_ARG, "cell %d: NULL device pointer", ci);
+    if (!aligned16(u_occ[ci]) || !aligned16(phi[ci]) || !aligned16(vphi[ci]))
+      return fail(FOCK_ERR_ARG, "cell %d: device pointers must be 16-byte aligned", ci);
     if (nphi[ci] < 1) return fail(FOCK_ERR_ARG, "cell %d: nphi must be >= 1", ci);
+    const size_t bu = (size_t)c.nk * c.nb * c.nr * sizeof(c128), bp = (size_t)c.nk * nphi[ci] * c.nr * sizeof(c128);
+    if (overlap(vphi[ci], bp, u_occ[ci], bu) || overlap(vphi[ci], bp, phi[ci], bp))
+      return fail(FOCK_ERR_ARG, "cell %d: vphi overlaps an input array", ci);
   }
-  for (int ci = 0; ci < (int)p->cells.size(); ++ci) {
-    Cell& c = p->cells[ci];
-    if ((s = p->general(c, (const c128*)phi[ci], nphi[ci], (const c128*)u_occ[ci], (const c128*)u_occ[ci], c.nb,
-                        (c128*)vphi[ci], -1.0 / c.nk, false, (hipStream_t)stream)) != FOCK_OK)
-      return s;
+  if (p->prec != FOCK_FP32_COMP || nc > kMaxBatchCells) {
+    // the plain FP64 path runs the cells one after another
+    for (int ci = 0; ci < nc; ++ci) {
+      Cell& c = p->cells[ci];
+      if ((s = p->general(c, (const c128*)phi[ci], nphi[ci], (const c128*)u_occ[ci], (const c128*)u_occ[ci], c.nb,
+                          (c128*)vphi[ci], -1.0 / c.nk, false, (hipStream_t)stream)) != FOCK_OK)
+        return s;
+    }
+    return FOCK_OK;
   }
-  return FOCK_OK;
+  return p->run_batched(u_occ, phi, nphi, vphi, (hipStream_t)stream);
 }

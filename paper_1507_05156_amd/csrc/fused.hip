@@ -45,10 +45,15 @@ constexpr bool fused_acc_in_regs() {
   return N <= 24;
 }
 
-namespace {
+template <int N>
+constexpr int fused_lds_elems() {
+  constexpr int NPH = fused_nph<N>();
+  constexpr int H = N / NPH, NBK = N / NPH;
+  constexpr int A = N * N * H, B = NBK * N * (N + 1);
+  return A > B ? A : B;
+}
 
-// loads issued back to back before the scheduler may move work across them
-constexpr int kLoadChunk = FOCKMI_LOAD_CHUNK;
+namespace {
 
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   const double t = s + x;
@@ -57,29 +62,25 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = t;
 }
 
-// occupancy target handed to the register allocator: waves per SIMD that the
-// LDS footprint allows (N = 24 runs one 9-wave workgroup per CU)
-template <int N>
-constexpr int fused_waves_per_eu() {
-  return N == 24 ? 3 : 4;
-}
-
-template <int N>
-__global__ void __launch_bounds__(N * N) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<N>())))
-fused_apply_kernel(FusedArgs a) {
-  constexpr int NT = N * N;
+// One work item (target field X[kt][s]) of the fused pair computation, run by a
+// workgroup of NT >= N*N threads. Threads t >= N*N are twins: they repeat the
+// work of thread t mod N*N (same loads, same LDS values to the same addresses,
+// which keeps every wave on the same straight-line code) and their FP64 stores
+// are steered past the end of the buffer, where raw buffer stores are dropped.
+template <int N, int NT>
+__device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc_slot, c64* __restrict__ lds) {
+  constexpr int NTI = N * N;
   constexpr int NR = N * N * N;
   constexpr int NPH = fused_nph<N>();
   constexpr int H = N / NPH;       // width of one round of the x<->y transpose (along m3)
-  constexpr int TPG = NT / NPH;    // threads per round
+  constexpr int TPG = NTI / NPH;   // threads per round
   constexpr int NBK = N / NPH;     // l1 values per round of the y<->z transpose
   constexpr bool ACCREG = fused_acc_in_regs<N>();
-  constexpr int LDS_A = N * N * H;
-  constexpr int LDS_B = NBK * N * (N + 1);
-  constexpr int LDS = LDS_A > LDS_B ? LDS_A : LDS_B;
-  __shared__ c64 lds[LDS];
+  static_assert(NT >= NTI, "workgroup too small");
 
-  const int t = threadIdx.x;
+  const int tr = threadIdx.x;
+  const bool twin = NT > NTI && tr >= NTI;
+  const int t = NT > NTI ? tr % NTI : tr;
   // round indices are wave-uniform (rounds are whole waves); readfirstlane
   // lets the compiler branch on them instead of masking lanes
   const int grp = __builtin_amdgcn_readfirstlane(t / TPG);
@@ -90,31 +91,22 @@ fused_apply_kernel(FusedArgs a) {
   const int gyz = __builtin_amdgcn_readfirstlane(chi / NBK);  // round of the y<->z transpose
   const int lrow = chi % NBK;
 
-  // work item of this workgroup
-  int b = blockIdx.x;
-  if (a.xcd_map) {
-    const int nwg = gridDim.x;
-    const int q = nwg / 8, rem = nwg % 8;
-    const int x = b % 8, r = b / 8;
-    b = x * q + (x < rem ? x : rem) + r;
-  }
-  const int item = a.item0 + b;
   const int kt = item / a.nx;
   const int s = item % a.nx;
 
   // byte offsets: x-phase element (m1, m2=chi, m3=clo) is at voff_x + m1 * N*N*8;
-  // table and FP32 partial sums are value-major: (v, t) at (v * NT + t) * size
+  // table and FP32 partial sums are value-major: (v, t) at (v * NTI + t) * size
   const unsigned voff_x = (unsigned)((chi * N + clo) * 8);
-  const unsigned voff_x128 = 2u * voff_x;
+  const unsigned voff_f = twin ? 0xF0000000u : 2u * voff_x;  // FP64 stores of twins are dropped
   const unsigned voff_t4 = (unsigned)(t * 4);
   const unsigned voff_t8 = (unsigned)(t * 8);
-  constexpr unsigned FB64 = NR * 8u;   // bytes of one complex64 field
+  constexpr unsigned FB64 = NR * 8u;  // bytes of one complex64 field
   constexpr unsigned FB128 = NR * 16u;
 
   const rsrc_t rX = make_rsrc(a.X + ((long)kt * a.nx + s) * NR, FB64);
   const rsrc_t rOut = make_rsrc(a.out + ((long)kt * a.nx + s) * NR, FB128);
   const rsrc_t rComp = make_rsrc(a.comp + ((long)kt * a.nx + s) * NR, FB128);
-  const rsrc_t rAcc = make_rsrc(ACCREG ? a.X : a.accs + (long)blockIdx.x * NR, ACCREG ? 0u : FB64);
+  const rsrc_t rAcc = make_rsrc(ACCREG ? a.X : a.accs + (long)acc_slot * NR, ACCREG ? 0u : FB64);
 
   c64 acc[ACCREG ? N : 1];
 
@@ -129,9 +121,8 @@ fused_apply_kernel(FusedArgs a) {
       c64 v[N];
 #pragma unroll
       for (int m1 = 0; m1 < N; ++m1) {
-        const unsigned so = (unsigned)(m1 * NT * 8);
+        const unsigned so = (unsigned)(m1 * NTI * 8);
         v[m1] = cmulc(ld_c64(rP, voff_x, so), ld_c64(rX, voff_x, so));
-        if (m1 % kLoadChunk == kLoadChunk - 1) __builtin_amdgcn_sched_barrier(0);
       }
       fft<N, -1>(v);
       // x -> y
@@ -165,7 +156,7 @@ fused_apply_kernel(FusedArgs a) {
       }
       fft<N, -1>(v);
 #pragma unroll
-      for (int l3 = 0; l3 < N; ++l3) v[l3] = cscale(v[l3], ld_f32(rK, voff_t4, (unsigned)(l3 * NT * 4)));
+      for (int l3 = 0; l3 < N; ++l3) v[l3] = cscale(v[l3], ld_f32(rK, voff_t4, (unsigned)(l3 * NTI * 4)));
       fft<N, +1>(v);
       // z -> y
 #pragma unroll
@@ -201,8 +192,7 @@ fused_apply_kernel(FusedArgs a) {
       const bool last_j = (j == a.nb - 1);
 #pragma unroll
       for (int m1 = 0; m1 < N; ++m1) {
-        const unsigned so = (unsigned)(m1 * NT * 8);
-        if (m1 % kLoadChunk == 0) __builtin_amdgcn_sched_barrier(0);
+        const unsigned so = (unsigned)(m1 * NTI * 8);
         const c64 prod = cmul(ld_c64(rM, voff_x, so), v[m1]);
         c64 tot;
         if constexpr (ACCREG) {
@@ -218,28 +208,27 @@ fused_apply_kernel(FusedArgs a) {
         // fold the FP32 band sum of this k' into the FP64 running sum
 #pragma unroll
         for (int m1 = 0; m1 < N; ++m1) {
-          const unsigned so = (unsigned)(m1 * NT * 16);
-          if (m1 % kLoadChunk == 0) __builtin_amdgcn_sched_barrier(0);
+          const unsigned so = (unsigned)(m1 * NTI * 16);
           const double xr = a.scale * (double)v[m1].re;
           const double xi = a.scale * (double)v[m1].im;
           double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
           if (!first_ks || a.accumulate) {
-            const c128 o = ld_c128(rOut, voff_x128, so);
+            const c128 o = ld_c128(rOut, voff_f, so);
             sr = o.re;
             si = o.im;
           }
           if (!first_ks) {
-            const c128 c = ld_c128(rComp, voff_x128, so);
+            const c128 c = ld_c128(rComp, voff_f, so);
             cr = c.re;
             ci = c.im;
           }
           neumaier(sr, cr, xr);
           neumaier(si, ci, xi);
           if (last_ks) {
-            st_c128(c128{sr + cr, si + ci}, rOut, voff_x128, so);
+            st_c128(c128{sr + cr, si + ci}, rOut, voff_f, so);
           } else {
-            st_c128(c128{sr, si}, rOut, voff_x128, so);
-            st_c128(c128{cr, ci}, rComp, voff_x128, so);
+            st_c128(c128{sr, si}, rOut, voff_f, so);
+            st_c128(c128{cr, ci}, rComp, voff_f, so);
           }
         }
       }
@@ -247,29 +236,92 @@ fused_apply_kernel(FusedArgs a) {
   }
 }
 
-template <int N>
+// one workgroup per target; WPE is the waves-per-SIMD target given to the
+// register allocator (a tunable: more waves, or more registers per wave)
+template <int N, int WPE>
+__global__ void __launch_bounds__(N * N) __attribute__((amdgpu_waves_per_eu(WPE)))
+fused_apply_kernel(FusedArgs a) {
+  __shared__ c64 lds[fused_lds_elems<N>()];
+  int b = blockIdx.x;
+  if (a.xcd_map) {
+    // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of targets so that workgroups sharing an L2 share k and K_q
+    const int nwg = gridDim.x;
+    const int q = nwg / 8, rem = nwg % 8;
+    const int x = b % 8, r = b / 8;
+    b = x * q + (x < rem ? x : rem) + r;
+  }
+  fused_item<N, N * N>(a, a.item0 + b, blockIdx.x, lds);
+}
+
+// Persistent workgroups of NT threads pop (cell, target) items from a queue
+// ordered by decreasing cost until it is empty; every item runs the code path
+// of its own grid length.
+template <int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT <= 576 ? 2 : 4)))
+fused_batched_kernel(BatchArgs B) {
+  constexpr int L24 = fused_lds_elems<24>(), L32 = fused_lds_elems<32>();
+  __shared__ c64 lds[NT > 576 ? L32 : L24];
+  __shared__ int it_sh;
+  for (;;) {
+    if (threadIdx.x == 0) it_sh = atomicAdd(B.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(it_sh);
+    __syncthreads();
+    if (it >= B.total) return;
+    const int cell = __builtin_amdgcn_readfirstlane(B.queue[2 * it]);
+    const int item = __builtin_amdgcn_readfirstlane(B.queue[2 * it + 1]);
+    const FusedArgs& a = B.cells[cell];
+    switch (a.n) {
+      case 16: fused_item<16, NT>(a, item, blockIdx.x, lds); break;
+      case 20: fused_item<20, NT>(a, item, blockIdx.x, lds); break;
+      case 24: fused_item<24, NT>(a, item, blockIdx.x, lds); break;
+      default:
+        if constexpr (NT >= 1024) fused_item<32, NT>(a, item, blockIdx.x, lds);
+        break;
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(int* c) { *c = 0; }
+
+template <int N, int WPE>
 hipError_t launch_n(const FusedArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(fused_apply_kernel<N>, dim3(a.nitems), dim3(N * N), 0, st, a);
+  hipLaunchKernelGGL((fused_apply_kernel<N, WPE>), dim3(a.nitems), dim3(N * N), 0, st, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-size_t fused_acc_scratch_elems(int n, int nitems) {
+size_t fused_acc_scratch_elems(int n, int nslots) {
   switch (n) {
-    case 32: return fused_acc_in_regs<32>() ? 0 : (size_t)nitems * 32 * 32 * 32;
+    case 32: return fused_acc_in_regs<32>() ? 0 : (size_t)nslots * 32 * 32 * 32;
     default: return 0;
   }
 }
 
-hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st) {
+int fused_variants(int n) { return (n == 16 || n == 20) ? 2 : 1; }
+
+hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant) {
   switch (n) {
-    case 16: return launch_n<16>(a, st);
-    case 20: return launch_n<20>(a, st);
-    case 24: return launch_n<24>(a, st);
-    case 32: return launch_n<32>(a, st);
+    case 16: return variant == 1 ? launch_n<16, 2>(a, st) : launch_n<16, 4>(a, st);
+    case 20: return variant == 1 ? launch_n<20, 2>(a, st) : launch_n<20, 4>(a, st);
+    case 24: return launch_n<24, 3>(a, st);
+    case 32: return launch_n<32, 4>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+int batched_threads(int nmax) { return nmax > 24 ? 1024 : 576; }
+
+hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, b.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nthreads == 576) hipLaunchKernelGGL(fused_batched_kernel<576>, dim3(nwg), dim3(576), 0, st, b);
+  else if (nthreads == 1024) hipLaunchKernelGGL(fused_batched_kernel<1024>, dim3(nwg), dim3(1024), 0, st, b);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace fockmi

@@ -51,10 +51,24 @@ struct FusedArgs {
   double scale;       // -1/N_k
   int accumulate;     // 1: add to the existing out
   int xcd_map;        // 1: map workgroups so that one XCD runs the targets of one k
+  int n;              // grid length of this cell (batched launch)
 };
-// n in {16, 20, 24, 32}; returns hipErrorInvalidValue otherwise
-hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st);
-size_t fused_acc_scratch_elems(int n, int nitems);  // c64 elements needed in accs (0 if registers)
+// n in {16, 20, 24, 32}; variant < fused_variants(n) selects the register/occupancy target
+hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant = 0);
+int fused_variants(int n);
+size_t fused_acc_scratch_elems(int n, int nslots);  // c64 elements needed in accs (0 if registers)
+
+// Persistent launch over several cells: nwg workgroups of nthreads pop items
+// (queue[2i] = cell, queue[2i+1] = target item) until `total` are taken.
+constexpr int kMaxBatchCells = 8;
+struct BatchArgs {
+  FusedArgs cells[kMaxBatchCells];
+  const int* queue;
+  int* counter;
+  int total;
+};
+int batched_threads(int nmax);  // workgroup size for a batch whose largest grid length is nmax
+hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipStream_t st);
 
 // ---- helpers ---------------------------------------------------------------
 hipError_t launch_to_c64(c64* dst, const c128* src, long count, hipStream_t st);

@@ -165,6 +165,7 @@ void Plan::destroy() {
   for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &psi0, &phiA,
                     &phiB, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms, &red6, &vloc_buf})
     b->release();
+  bstate.release();
   if (host_pinned) (void)hipHostFree(host_pinned);
   host_pinned = nullptr;
   magic = 0;

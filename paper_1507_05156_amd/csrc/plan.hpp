@@ -9,6 +9,7 @@
 
 #include "../../include/fockmi.h"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 namespace fockmi {
 
@@ -43,6 +44,22 @@ struct Cell {
   DevBuf kvec;                // double[nk][3] k-points on the device
 };
 
+// state of the batched persistent launch (fock_apply_batched): buffers whose
+// addresses a captured graph refers to, and the graph itself
+struct BatchState {
+  std::vector<const void*> key;  // u, phi, vphi pointers and nphi of every cell
+  DevBuf shadow_u[kMaxBatchCells], shadow_x[kMaxBatchCells], comp[kMaxBatchCells];
+  DevBuf accs, queue, counter;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  BatchArgs args{};
+  int nthreads = 0, nwg = 0, total = 0;
+  bool ready = false;
+  void reset_graph();
+  void release();
+};
+
 struct Plan {
   static constexpr unsigned kMagic = 0xF0C4C0DEu;
   unsigned magic = kMagic;
@@ -58,6 +75,14 @@ struct Plan {
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
   bool profiling = false;
+  // autotuning: the cache is read at plan creation when a path is given; missing
+  // keys are measured on first use and the file is rewritten
+  TuneCache tune;
+  bool tuning = false;
+  int use_graph = 1;
+  BatchState bstate;
+  int num_cus = 0;
+
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   double prof_ms = 0.0;
   long long prof_launches = 0;
@@ -85,6 +110,12 @@ struct Plan {
   fock_status h_apply(Cell& c, const c128* u, const c128* x, c128* out, const c128* base, double cre, double cim,
                       const double* vloc, const double a[3], double alpha, hipStream_t st);
   fock_status field_bufs(Cell& c, std::initializer_list<DevBuf*> bufs, int nfields_per_k);
+
+  // batched persistent launch (batched.hip)
+  fock_status run_batched(const void* const* u, const void* const* phi, const int* nphi, void* const* vphi,
+                          hipStream_t st);
+  std::string key_for(const Cell& c, int nx, const char* what) const;
+  void save_tune();
 };
 
 }  // namespace fockmi
