@@ -138,9 +138,12 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
  * assumes for occupied orbitals). psi: device [nk][nb][N_r] complex128 in place. */
 fock_status fock_orthonormalize(fockmi_plan plan, int cell, void* psi, void* stream);
 
-/* All cells of the plan in one persistent launch (FOCK_FP32_COMP plans):
- * u_occ[c], phi[c], vphi[c] as in fock_apply for cell c, nphi[c] targets.
- * Host arrays of device pointers, one entry per cell. Stream-ordered. */
+/* All cells of the plan in one persistent launch (FOCK_FP32_COMP plans with up
+ * to 8 cells of grid lengths 16, 20, 24), replayed from a captured hipGraph
+ * while the same buffers are passed: u_occ[c], phi[c], vphi[c] as in
+ * fock_apply for cell c, nphi[c] targets. Host arrays of device pointers, one
+ * entry per cell. Other plans run their cells one after another.
+ * Stream-ordered. */
 fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
                                const int* nphi, void* const* vphi, void* stream);
 

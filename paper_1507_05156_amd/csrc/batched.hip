@@ -207,8 +207,10 @@ extern "C" fock_status fock_apply_batched(fockmi_plan plan, const void* const* u
     if (overlap(vphi[ci], bp, u_occ[ci], bu) || overlap(vphi[ci], bp, phi[ci], bp))
       return fail(FOCK_ERR_ARG, "cell %d: vphi overlaps an input array", ci);
   }
-  if (p->prec != FOCK_FP32_COMP || nc > kMaxBatchCells) {
-    // the plain FP64 path runs the cells one after another
+  int nmax = 0;
+  for (const Cell& c : p->cells) nmax = std::max(nmax, c.geom.n1);
+  if (p->prec != FOCK_FP32_COMP || nc > kMaxBatchCells || batched_threads(nmax) == 0) {
+    // the plain FP64 path, and plans with a 32^3 cell, run the cells one after another
     for (int ci = 0; ci < nc; ++ci) {
       Cell& c = p->cells[ci];
       if ((s = p->general(c, (const c128*)phi[ci], nphi[ci], (const c128*)u_occ[ci], (const c128*)u_occ[ci], c.nb,

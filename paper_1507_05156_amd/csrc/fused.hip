@@ -256,12 +256,12 @@ fused_apply_kernel(FusedArgs a) {
 
 // Persistent workgroups of NT threads pop (cell, target) items from a queue
 // ordered by decreasing cost until it is empty; every item runs the code path
-// of its own grid length.
+// of its own grid length (16, 20 or 24).
 template <int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT <= 576 ? 2 : 4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 fused_batched_kernel(BatchArgs B) {
-  constexpr int L24 = fused_lds_elems<24>(), L32 = fused_lds_elems<32>();
-  __shared__ c64 lds[NT > 576 ? L32 : L24];
+  static_assert(NT == 576, "the persistent kernel serves grid lengths up to 24");
+  __shared__ c64 lds[fused_lds_elems<24>()];
   __shared__ int it_sh;
   for (;;) {
     if (threadIdx.x == 0) it_sh = atomicAdd(B.counter, 1);
@@ -275,10 +275,7 @@ fused_batched_kernel(BatchArgs B) {
     switch (a.n) {
       case 16: fused_item<16, NT>(a, item, blockIdx.x, lds); break;
       case 20: fused_item<20, NT>(a, item, blockIdx.x, lds); break;
-      case 24: fused_item<24, NT>(a, item, blockIdx.x, lds); break;
-      default:
-        if constexpr (NT >= 1024) fused_item<32, NT>(a, item, blockIdx.x, lds);
-        break;
+      default: fused_item<24, NT>(a, item, blockIdx.x, lds); break;
     }
   }
 }
@@ -312,15 +309,14 @@ hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int var
   }
 }
 
-int batched_threads(int nmax) { return nmax > 24 ? 1024 : 576; }
+int batched_threads(int nmax) { return nmax > 24 ? 0 : 576; }
 
 hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipStream_t st) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, b.counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (nthreads == 576) hipLaunchKernelGGL(fused_batched_kernel<576>, dim3(nwg), dim3(576), 0, st, b);
-  else if (nthreads == 1024) hipLaunchKernelGGL(fused_batched_kernel<1024>, dim3(nwg), dim3(1024), 0, st, b);
-  else return hipErrorInvalidValue;
+  if (nthreads != 576) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused_batched_kernel<576>, dim3(nwg), dim3(576), 0, st, b);
   return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ struct BatchArgs {
   int* counter;
   int total;
 };
-int batched_threads(int nmax);  // workgroup size for a batch whose largest grid length is nmax
+int batched_threads(int nmax);  // workgroup size for a batch whose largest grid length is nmax (0: none)
 hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipStream_t st);
 
 // ---- helpers ---------------------------------------------------------------

@@ -167,3 +167,17 @@ def test_plan_errors_on_device(device):
     with pytest.raises(FockError):
         from paper_1507_05156_amd.api import Plan
         Plan(dict(n=16, a=cell, kpts=np.vstack([kp, kp[:1]]), nb=4, omega=OMEGA))
+
+
+@pytest.mark.parametrize("n", [24, 32])
+def test_fused_form_is_deterministic(device, n):
+    """Two applications on the same inputs give bitwise-equal FP32-form results."""
+    print(f"[gpu] determinism n={n}", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(3, cell, 1, 1)
+    u = synth.orbitals(n, cell, kp, 3, seed=600 + n)
+    plan = make_plan(cell, kp, 3, n, "fp32")
+    ud = to_dev(u)
+    a = plan.apply(ud).clone()
+    b = plan.apply(ud)
+    assert bool((a == b).all())
