@@ -51,7 +51,8 @@ def test_workload0_full_parity(device, prec):
     e_ref = oracle.exchange_energy(u, kp, cell, OMEGA, V=ref)
     e = plan.energy(to_dev(u))
     assert abs(e.real - e_ref.real) / abs(e_ref.real) < TOL[prec]
-    assert e.real < 0 and abs(e.imag) < 1e-10 * abs(e.real)
+    # the imaginary part is rounding only: FP64 sums of the FP32-form products carry ~1e-10
+    assert e.real < 0 and abs(e.imag) < (1e-12 if prec == "fp64" else 1e-8) * abs(e.real)
 
 
 @pytest.mark.parametrize("n", [16, 20, 24, 32])
