@@ -67,9 +67,14 @@ __device__ __forceinline__ float ld_f32(rsrc_t r, unsigned voff, unsigned soff) 
 __device__ __forceinline__ cx<double> ld_c128(rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+// A complex128 is stored as two 64-bit buffer stores. A 128-bit buffer store
+// whose offset comes from an SGPR, with its data VGPRs rewritten by the next
+// VALU instructions, was seen to write wrong data now and then (no wait states
+// are inserted for that form); 64-bit stores carry no such hazard.
 __device__ __forceinline__ void st_c128(cx<double> v, rsrc_t r, unsigned voff, unsigned soff) {
-  using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0u, 0u, 0));
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, voff, soff, 0);
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v.re), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v.im), r, voff + 8u, soff, 0);
 }
 
 // ---------------------------------------------------------------- static_for
