@@ -36,14 +36,22 @@ int fused_phases(int n) {
   }
 }
 
-#ifndef FOCKMI_LOAD_CHUNK
-#define FOCKMI_LOAD_CHUNK 8
-#endif
-
 template <int N>
 constexpr bool fused_acc_in_regs() {
   return N <= 24;
 }
+
+// Global loads are issued in groups whose results are consumed only after the
+// whole group is in flight, so a pair costs a few memory round trips instead
+// of one per line element. Group sizes per grid length: pair-product operands,
+// kernel values, multipliers (0: element by element, where the registers are
+// full, as for N = 32 whose multiplier loads would spill).
+template <int N>
+constexpr int grp_px() { return N == 16 ? 8 : (N <= 24 ? 4 : N); }
+template <int N>
+constexpr int grp_k() { return N <= 24 ? N : 8; }
+template <int N>
+constexpr int grp_m() { return N == 16 ? 8 : (N <= 24 ? 4 : 0); }
 
 template <int N>
 constexpr int fused_lds_elems() {
@@ -119,11 +127,17 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
       const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
       const rsrc_t rM = make_rsrc(a.M + ((long)ks * a.nb + j) * NR, FB64);
       c64 v[N];
-#pragma unroll
-      for (int m1 = 0; m1 < N; ++m1) {
-        const unsigned so = (unsigned)(m1 * NTI * 8);
-        v[m1] = cmulc(ld_c64(rP, voff_x, so), ld_c64(rX, voff_x, so));
-      }
+      static_for<(N + grp_px<N>() - 1) / grp_px<N>()>([&](auto cc) {
+        constexpr int G = grp_px<N>(), C0 = decltype(cc)::value * G, CN = (N - C0 < G) ? N - C0 : G;
+        c64 p[CN], x[CN];
+        static_for<CN>([&](auto q) {
+          const unsigned so = (unsigned)((C0 + decltype(q)::value) * NTI * 8);
+          p[q] = ld_c64(rP, voff_x, so);
+          x[q] = ld_c64(rX, voff_x, so);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<CN>([&](auto q) { v[C0 + decltype(q)::value] = cmulc(p[q], x[q]); });
+      });
       fft<N, -1>(v);
       // x -> y
 #pragma unroll
@@ -155,8 +169,13 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
         __syncthreads();
       }
       fft<N, -1>(v);
-#pragma unroll
-      for (int l3 = 0; l3 < N; ++l3) v[l3] = cscale(v[l3], ld_f32(rK, voff_t4, (unsigned)(l3 * NTI * 4)));
+      static_for<(N + grp_k<N>() - 1) / grp_k<N>()>([&](auto cc) {
+        constexpr int G = grp_k<N>(), C0 = decltype(cc)::value * G, CN = (N - C0 < G) ? N - C0 : G;
+        float kv[CN];
+        static_for<CN>([&](auto q) { kv[q] = ld_f32(rK, voff_t4, (unsigned)((C0 + decltype(q)::value) * NTI * 4)); });
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<CN>([&](auto q) { v[C0 + decltype(q)::value] = cscale(v[C0 + decltype(q)::value], kv[q]); });
+      });
       fft<N, +1>(v);
       // z -> y
 #pragma unroll
@@ -190,19 +209,42 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
       fft<N, +1>(v);
 
       const bool last_j = (j == a.nb - 1);
+      if constexpr (ACCREG) {
+        static_assert(N % grp_m<N>() == 0, "multiplier groups must tile the line");
+        static_for<N / grp_m<N>()>([&](auto cc) {
+          constexpr int G = grp_m<N>(), C0 = decltype(cc)::value * G;
+          c64 mv[G];
+          static_for<G>([&](auto q) { mv[q] = ld_c64(rM, voff_x, (unsigned)((C0 + decltype(q)::value) * NTI * 8)); });
+          __builtin_amdgcn_sched_barrier(0);
+          static_for<G>([&](auto q) {
+            constexpr int m1 = C0 + decltype(q)::value;
+            const c64 prod = cmul(mv[q], v[m1]);
+            acc[m1] = (j == 0) ? prod : acc[m1] + prod;
+            v[m1] = acc[m1];
+          });
+        });
+      } else {
+        // the position of j in the band loop is uniform: one branch per pair
+        // selects the accumulator traffic, none per element
+        auto mac = [&](auto load_acc, auto store_acc) {
 #pragma unroll
-      for (int m1 = 0; m1 < N; ++m1) {
-        const unsigned so = (unsigned)(m1 * NTI * 8);
-        const c64 prod = cmul(ld_c64(rM, voff_x, so), v[m1]);
-        c64 tot;
-        if constexpr (ACCREG) {
-          tot = (j == 0) ? prod : acc[m1] + prod;
-          acc[m1] = tot;
+          for (int m1 = 0; m1 < N; ++m1) {
+            const unsigned so = (unsigned)(m1 * NTI * 8);
+            c64 tot = cmul(ld_c64(rM, voff_x, so), v[m1]);
+            if constexpr (decltype(load_acc)::value) tot = ld_c64(rAcc, voff_t8, so) + tot;
+            if constexpr (decltype(store_acc)::value) st_c64(tot, rAcc, voff_t8, so);
+            v[m1] = tot;
+          }
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        if (j == 0) {
+          if (last_j) mac(F{}, F{});
+          else mac(F{}, T{});
         } else {
-          tot = (j == 0) ? prod : ld_c64(rAcc, voff_t8, so) + prod;
-          if (!last_j) st_c64(tot, rAcc, voff_t8, so);
+          if (last_j) mac(T{}, F{});
+          else mac(T{}, T{});
         }
-        v[m1] = tot;
       }
       if (last_j) {
         // fold the FP32 band sum of this k' into the FP64 running sum
