@@ -50,8 +50,9 @@ typedef enum {
 
 typedef enum {
   FOCK_FP64 = 0,         /* plain FP64 path: one stage per kernel through HBM */
-  FOCK_FP32_COMP = 1     /* fused pair kernel: complex64 pair FFTs, FP32 band partial sums,
-                            Neumaier-compensated FP64 accumulation over k' and j */
+  FOCK_FP32_COMP = 1     /* fused pair kernel: complex64 pair FFTs; the sum over the bands j
+                            of one k' in FP32, added into an FP64 running sum over k' with
+                            Neumaier compensation */
 } fock_prec;
 
 typedef struct {
