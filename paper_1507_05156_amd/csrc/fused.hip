@@ -63,6 +63,22 @@ constexpr int fused_lds_elems() {
 
 namespace {
 
+// LDS element at a per-thread byte offset plus a compile-time byte offset; the
+// constant folds into the instruction's 16-bit immediate when below 64 KiB.
+template <unsigned C>
+__device__ __forceinline__ c64& lds_at(c64* lds, unsigned off) {
+  static_assert(C < 65536u, "LDS immediate offset out of range");
+  return *reinterpret_cast<c64*>(reinterpret_cast<char*>(lds) + off + C);
+}
+
+// Hides a value from loop-invariant code motion: addresses derived from it are
+// formed where they are used (base register + immediate) instead of being
+// hoisted out of the pair loop, one register each, and spilled.
+__device__ __forceinline__ unsigned opaque(unsigned x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   const double t = s + x;
   if (fabs(s) >= fabs(x)) c += (s - t) + x;
@@ -98,6 +114,20 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   const int chi = tl / H;        // m2 in the x phase, l1 in the y and z phases
   const int gyz = __builtin_amdgcn_readfirstlane(chi / NBK);  // round of the y<->z transpose
   const int lrow = chi % NBK;
+
+  // LDS byte offsets of this thread's elements in the four transposes:
+  //   x side of x<->y : element l1 at lx + l1 * SX        (SX = N*H*8)
+  //   y side of x<->y : element m2 at ly + m2 * H*8
+  //   y side of y<->z : element l2 at lyz + l2 * (N+1)*8
+  //   z side of y<->z : element m3 at lz + m3 * 8
+  // Only the x side spans more than 64 KiB; its elements from L1S on are
+  // addressed from a second base.
+  constexpr unsigned SX = (unsigned)(N * H * 8);
+  constexpr int L1S = (int)((65535u / SX) + 1) < N ? (int)((65535u / SX) + 1) : N;
+  const unsigned lx0 = (unsigned)((chi * H + hl) * 8);
+  const unsigned ly0 = (unsigned)((chi * N * H + hl) * 8);
+  const unsigned lyz0 = (unsigned)((lrow * N * (N + 1) + clo) * 8);
+  const unsigned lz0 = (unsigned)((lrow * N + clo) * (N + 1) * 8);
 
   const int kt = item / a.nx;
   const int s = item % a.nx;
@@ -143,13 +173,17 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
 #pragma unroll
       for (int g = 0; g < NPH; ++g) {
         if (grp == g) {
-#pragma unroll
-          for (int l1 = 0; l1 < N; ++l1) lds[(l1 * N + chi) * H + hl] = v[l1];
+          const unsigned b0 = opaque(lx0), b1 = opaque(lx0 + L1S * SX);
+          static_for<N>([&](auto l1) {
+            constexpr int L = decltype(l1)::value;
+            if constexpr (L < L1S) lds_at<L * SX>(lds, b0) = v[L];
+            else lds_at<(L - L1S) * SX>(lds, b1) = v[L];
+          });
         }
         __syncthreads();
         if (grp == g) {
-#pragma unroll
-          for (int m2 = 0; m2 < N; ++m2) v[m2] = lds[(chi * N + m2) * H + hl];
+          const unsigned b = opaque(ly0);
+          static_for<N>([&](auto m2) { v[m2] = lds_at<decltype(m2)::value * H * 8>(lds, b); });
         }
         __syncthreads();
       }
@@ -158,13 +192,13 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
 #pragma unroll
       for (int g = 0; g < NPH; ++g) {
         if (gyz == g) {
-#pragma unroll
-          for (int l2 = 0; l2 < N; ++l2) lds[(lrow * N + l2) * (N + 1) + clo] = v[l2];
+          const unsigned b = opaque(lyz0);
+          static_for<N>([&](auto l2) { lds_at<decltype(l2)::value * (N + 1) * 8>(lds, b) = v[l2]; });
         }
         __syncthreads();
         if (gyz == g) {
-#pragma unroll
-          for (int m3 = 0; m3 < N; ++m3) v[m3] = lds[(lrow * N + clo) * (N + 1) + m3];
+          const unsigned b = opaque(lz0);
+          static_for<N>([&](auto m3) { v[m3] = lds_at<decltype(m3)::value * 8>(lds, b); });
         }
         __syncthreads();
       }
@@ -181,13 +215,13 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
 #pragma unroll
       for (int g = 0; g < NPH; ++g) {
         if (gyz == g) {
-#pragma unroll
-          for (int m3 = 0; m3 < N; ++m3) lds[(lrow * N + clo) * (N + 1) + m3] = v[m3];
+          const unsigned b = opaque(lz0);
+          static_for<N>([&](auto m3) { lds_at<decltype(m3)::value * 8>(lds, b) = v[m3]; });
         }
         __syncthreads();
         if (gyz == g) {
-#pragma unroll
-          for (int l2 = 0; l2 < N; ++l2) v[l2] = lds[(lrow * N + l2) * (N + 1) + clo];
+          const unsigned b = opaque(lyz0);
+          static_for<N>([&](auto l2) { v[l2] = lds_at<decltype(l2)::value * (N + 1) * 8>(lds, b); });
         }
         __syncthreads();
       }
@@ -196,13 +230,17 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
 #pragma unroll
       for (int g = 0; g < NPH; ++g) {
         if (grp == g) {
-#pragma unroll
-          for (int m2 = 0; m2 < N; ++m2) lds[(chi * N + m2) * H + hl] = v[m2];
+          const unsigned b = opaque(ly0);
+          static_for<N>([&](auto m2) { lds_at<decltype(m2)::value * H * 8>(lds, b) = v[m2]; });
         }
         __syncthreads();
         if (grp == g) {
-#pragma unroll
-          for (int l1 = 0; l1 < N; ++l1) v[l1] = lds[(l1 * N + chi) * H + hl];
+          const unsigned b0 = opaque(lx0), b1 = opaque(lx0 + L1S * SX);
+          static_for<N>([&](auto l1) {
+            constexpr int L = decltype(l1)::value;
+            if constexpr (L < L1S) v[L] = lds_at<L * SX>(lds, b0);
+            else v[L] = lds_at<(L - L1S) * SX>(lds, b1);
+          });
         }
         __syncthreads();
       }
