@@ -81,6 +81,79 @@ def cpu_baseline(u, kp, cell, omega, nsrc):
     return pairs / dt, dt, pairs, threads
 
 
+def _timed(fn, reps, torch):
+    """Average wall seconds of fn() over reps calls, bracketed by device synchronisation."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
+    """Timings of the other calls on the path, each on its own workload:
+    the batched persistent launch over three uneven cells (against the same cells
+    launched one by one, and against the plain FP64 path for the error), the FP64
+    adjoint and Taylor-4 step at 24^3 / 64 k / 16 bands, and E_x and the FP64
+    orthonormalisation at 32^3 / 216 k / 16 bands."""
+    out = {}
+    # ------------------------------------------- batched persistent launch (three cells)
+    cells, us = [], []
+    for ci in range(3):
+        a, kp, u = synth.workload(4, ci)
+        cells.append(dict(n=u.shape[2], a=a, kpts=kp, nb=u.shape[1], omega=omega))
+        us.append(torch.from_numpy(u).to(dev))
+    pairs = sum((c["kpts"].shape[0] * c["nb"]) ** 2 for c in cells)
+    pb = Plan(cells, prec="fp32")
+    pb.apply_batched(us)
+    t_batched = _timed(lambda: pb.apply_batched(us), 3, torch)
+    t_cells = _timed(lambda: [pb.apply(us[ci], cell=ci) for ci in range(3)], 3, torch)
+    outs = pb.apply_batched(us)
+    errs = []
+    for ci, c in enumerate(cells):
+        p64 = Plan(c, prec="fp64")
+        ref = p64.apply(us[ci])
+        nk = c["kpts"].shape[0]
+        rel = ((outs[ci] - ref).reshape(nk, -1).norm(dim=1) / ref.reshape(nk, -1).norm(dim=1)).max().item()
+        errs.append(rel)
+        del p64, ref
+    out["batched_3cells"] = {
+        "cells": "16^3/27 k/8 b + 20^3/64 k/12 b + 24^3/125 k/16 b", "pairs": pairs,
+        "persistent_graph_pairs_per_s": pairs / t_batched, "persistent_graph_ms": t_batched * 1e3,
+        "per_cell_launches_pairs_per_s": pairs / t_cells, "per_cell_launches_ms": t_cells * 1e3,
+        "max_rel_err_per_k_vs_fp64": max(errs), "rel_err_per_cell": errs}
+    del pb, us, outs
+    print(f"[bench] batched 3 cells: {pairs / t_batched:.4e} pairs/s (per-cell launches {pairs / t_cells:.4e})",
+          file=sys.stderr, flush=True)
+    # ------------------------------------------------ FP64 adjoint and Taylor-4 step, 24^3
+    a, kp, u = synth.workload(3)
+    nk, nb = u.shape[0], u.shape[1]
+    p3 = (nk * nb) ** 2
+    u3 = torch.from_numpy(u).to(dev)
+    plan = Plan(dict(n=u.shape[2], a=a, kpts=kp, nb=nb, omega=omega), prec="fp64")
+    g = torch.from_numpy(synth.random_fields(u.shape, seed=7)).to(dev)
+    plan.vjp(u3, u3, g)
+    t_vjp = _timed(lambda: plan.vjp(u3, u3, g), 1, torch)
+    psi = u3.clone()
+    t_step = _timed(lambda: plan.taylor_step(psi, [0.0, 0.0, 0.01], 0.02, 0.25), 1, torch)
+    t_apply = _timed(lambda: plan.apply(u3), 1, torch)
+    out["fp64_24cube_64k_16b"] = {
+        "pairs_per_apply": p3, "apply_ms": t_apply * 1e3, "apply_pairs_per_s": p3 / t_apply,
+        "vjp_ms": t_vjp * 1e3, "vjp_pair_ffts_per_s": 3 * p3 / t_vjp,
+        "taylor4_step_ms": t_step * 1e3, "taylor4_pair_ffts_per_s": 4 * p3 / t_step}
+    del plan, u3, g, psi
+    print(f"[bench] fp64 24^3: apply {t_apply * 1e3:.0f} ms, vjp {t_vjp * 1e3:.0f} ms, "
+          f"taylor step {t_step * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    # --------------------------------------------------- E_x and orthonormalisation, 32^3
+    t_e = _timed(lambda: plan32_c2.energy(ud_c2), 1, torch)
+    psi = ud_c2.clone()
+    t_o = _timed(lambda: plan32_c2.orthonormalize(psi), 1, torch)
+    out["c2_energy_fp32_ms"] = t_e * 1e3
+    out["c2_orthonormalize_fp64_ms"] = t_o * 1e3
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +162,8 @@ def main():
     ap.add_argument("--workload", type=int, default=2, help="2: 32^3/216k/16b (default); 1: 24^3/64k/16b")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed plain FP64 applications (0 = skip)")
     ap.add_argument("--cpu-sources", type=int, default=96, help="source k-points in the oracle sample (0 = skip)")
+    ap.add_argument("--extras", type=int, default=1, help="1: also time the batched launch, adjoint, Taylor step, "
+                    "energy and orthonormalisation")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -181,6 +256,8 @@ def main():
               file=sys.stderr, flush=True)
         del plan64, out64
 
+    extras = extra_legs(torch, np, synth, Plan, omega, dev, ud, plan32) if args.extras else None
+
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if args.cpu_sources > 0:
@@ -221,6 +298,8 @@ def main():
         "cpu_baseline": cpu,
     }
     rec.update(fp64)
+    if extras is not None:
+        rec["other_calls"] = extras
     print(json.dumps(rec))
 
 

@@ -2,8 +2,10 @@
 // from a captured hipGraph while the caller passes the same buffers.
 //
 // Per call: one complex64 shadow per orbital array (and per distinct target
-// array), a queue-counter reset (a one-thread kernel, no memset node), and the
-// persistent kernel over the (cell, target) queue ordered by decreasing cost.
+// array), a reset of the sub-queue counters (a one-thread kernel, no memset
+// node), and the persistent kernel over per-XCD sub-queues of (cell, target)
+// entries ordered by decreasing cost. With a tuning cache, the first call
+// measures the number of persistent workgroups per CU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +39,7 @@ void BatchState::release() {
   }
   accs.release();
   queue.release();
-  counter.release();
+  counters.release();
   if (cap) (void)hipStreamDestroy(cap);
   cap = nullptr;
   key.clear();
@@ -72,23 +74,47 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return item_cost(cells[x]) > item_cost(cells[y]); });
-    std::vector<int> q;
+    // entries (cell, target, second target or -1): a 16^3 entry carries two
+    // targets of its cell. Every cell's entries are split into kBatchQueues
+    // contiguous shares, one per sub-queue, cells in decreasing cost order.
+    std::vector<std::vector<int>> sub(kBatchQueues);
     for (int ci : order) {
       Cell& c = cells[ci];
       nmax = std::max(nmax, c.geom.n1);
-      for (int it = 0; it < c.nk * nphi[ci]; ++it) {
-        q.push_back(ci);
-        q.push_back(it);
+      const int ntg = c.nk * nphi[ci];
+      const int per = c.geom.n1 == 16 ? 2 : 1;
+      std::vector<int> ent;
+      for (int it = 0; it < ntg; it += per) {
+        ent.push_back(ci);
+        ent.push_back(it);
+        ent.push_back(per == 2 && it + 1 < ntg ? it + 1 : -1);
+      }
+      const int ne = (int)ent.size() / 3;
+      for (int x = 0; x < kBatchQueues; ++x) {
+        const int b = (int)((long)ne * x / kBatchQueues), e2 = (int)((long)ne * (x + 1) / kBatchQueues);
+        sub[x].insert(sub[x].end(), ent.begin() + 3 * b, ent.begin() + 3 * e2);
       }
     }
-    B.total = (int)q.size() / 2;
+    std::vector<int> q;
+    int qoff[kBatchQueues], qlen[kBatchQueues];
+    for (int x = 0; x < kBatchQueues; ++x) {
+      qoff[x] = (int)q.size() / 3;
+      qlen[x] = (int)sub[x].size() / 3;
+      q.insert(q.end(), sub[x].begin(), sub[x].end());
+    }
+    B.entries = (int)q.size() / 3;
     B.nthreads = batched_threads(nmax);
-    int mult = 1;
-    {
+    const std::string tkey = [&] {
       std::string k = arch_name() + "/fp32/batched";
       for (int ci = 0; ci < nc; ++ci) k += "/" + key_for(cells[ci], nphi[ci], "cell");
+      return k;
+    }();
+    int mult = 1;
+    bool measure = false;
+    {
       TuneEntry te;
-      if (tune.get(k, &te)) mult = std::max(1, (int)te.fields["wg_per_cu"]);
+      if (tune.get(tkey, &te)) mult = std::max(1, (int)te.fields["wg_per_cu"]);
+      else measure = tuning;
     }
     B.nwg = num_cus * mult;
     for (int ci = 0; ci < nc; ++ci) {
@@ -106,7 +132,7 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
                            "batched FP32 sums")) != FOCK_OK)
       return s;
     if ((s = B.queue.ensure(q.size() * sizeof(int), 0, "batched queue")) != FOCK_OK) return s;
-    if ((s = B.counter.ensure(sizeof(int), 0, "batched counter")) != FOCK_OK) return s;
+    if ((s = B.counters.ensure(kBatchQueues * sizeof(int), 0, "batched counters")) != FOCK_OK) return s;
     if ((e = hipMemcpy(B.queue.ptr, q.data(), q.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_fail(e, "upload queue");
     BatchArgs& A = B.args;
@@ -132,11 +158,53 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
       a.n = c.geom.n1;
     }
     A.queue = (const int*)B.queue.ptr;
-    A.counter = (int*)B.counter.ptr;
-    A.total = B.total;
+    A.counters = (int*)B.counters.ptr;
+    for (int x = 0; x < kBatchQueues; ++x) {
+      A.qoff[x] = qoff[x];
+      A.qlen[x] = qlen[x];
+    }
     if (!B.cap && (e = hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "capture stream");
     B.ready = true;
+    if (measure) {
+      // persistent workgroups per CU: each candidate runs the whole batch on
+      // this call's data (every run writes the same result)
+      for (int cid = 0; cid < nc; ++cid) {
+        Cell& c = cells[cid];
+        const long nu = (long)c.nk * c.nb * c.nr, nx = (long)c.nk * nphi[cid] * c.nr;
+        if ((e = launch_to_c64((c64*)B.shadow_u[cid].ptr, (const c128*)u[cid], nu, st)) != hipSuccess)
+          return hip_fail(e, "batched shadow");
+        if (phi[cid] != u[cid] &&
+            (e = launch_to_c64((c64*)B.shadow_x[cid].ptr, (const c128*)phi[cid], nx, st)) != hipSuccess)
+          return hip_fail(e, "batched shadow");
+      }
+      hipEvent_t e0, e1;
+      if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tuning event");
+      if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
+      double best = 1e300;
+      int bm = 1;
+      for (int m : {1, 2}) {
+        (void)hipEventRecord(e0, st);
+        if ((e = launch_fused_batched(B.args, B.nthreads, num_cus * m, st)) != hipSuccess)
+          return hip_fail(e, "persistent kernel");
+        (void)hipEventRecord(e1, st);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          bm = m;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      TuneEntry te;
+      te.fields["wg_per_cu"] = bm;
+      te.fields["ms"] = best;
+      tune.put(tkey, te);
+      save_tune();
+      B.nwg = num_cus * bm;
+    }
   }
 
   auto enqueue = [&](hipStream_t q) -> fock_status {

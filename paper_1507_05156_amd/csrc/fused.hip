@@ -86,13 +86,16 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = t;
 }
 
-// One work item (target field X[kt][s]) of the fused pair computation, run by a
-// workgroup of NT >= N*N threads. Threads t >= N*N are twins: they repeat the
-// work of thread t mod N*N (same loads, same LDS values to the same addresses,
-// which keeps every wave on the same straight-line code) and their FP64 stores
-// are steered past the end of the buffer, where raw buffer stores are dropped.
-template <int N, int NT>
-__device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc_slot, c64* __restrict__ lds) {
+// One work item (target field X[kt][s]) of the fused pair computation, run by
+// the N*N threads t = 0 .. N*N-1 of one thread group, with `lds` its own LDS
+// region. Twin threads (twin = true) repeat the work of thread t of a real
+// group (same loads, same LDS values to the same addresses, which keeps every
+// wave on the same straight-line code); their FP64 stores are steered past the
+// end of the buffer, where raw buffer stores are dropped. `item` must be
+// uniform over each wave.
+template <int N>
+__device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc_slot, c64* __restrict__ lds,
+                                           int t, bool twin) {
   constexpr int NTI = N * N;
   constexpr int NR = N * N * N;
   constexpr int NPH = fused_nph<N>();
@@ -100,11 +103,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   constexpr int TPG = NTI / NPH;   // threads per round
   constexpr int NBK = N / NPH;     // l1 values per round of the y<->z transpose
   constexpr bool ACCREG = fused_acc_in_regs<N>();
-  static_assert(NT >= NTI, "workgroup too small");
-
-  const int tr = threadIdx.x;
-  const bool twin = NT > NTI && tr >= NTI;
-  const int t = NT > NTI ? tr % NTI : tr;
+  item = __builtin_amdgcn_readfirstlane(item);
   // round indices are wave-uniform (rounds are whole waves); readfirstlane
   // lets the compiler branch on them instead of masking lanes
   const int grp = __builtin_amdgcn_readfirstlane(t / TPG);
@@ -331,36 +330,66 @@ fused_apply_kernel(FusedArgs a) {
     const int x = b % 8, r = b / 8;
     b = x * q + (x < rem ? x : rem) + r;
   }
-  fused_item<N, N * N>(a, a.item0 + b, blockIdx.x, lds);
+  fused_item<N>(a, a.item0 + b, blockIdx.x, lds, threadIdx.x, false);
 }
 
-// Persistent workgroups of NT threads pop (cell, target) items from a queue
-// ordered by decreasing cost until it is empty; every item runs the code path
-// of its own grid length (16, 20 or 24).
+// Persistent workgroups of NT threads pop queue entries (cell, target, second
+// target or -1) until every sub-queue is empty. Each XCD has a sub-queue of its
+// own (a contiguous share of every cell's targets, so that targets sharing k and
+// K_q meet in one L2) and moves on to the other sub-queues when it runs dry.
+// An entry runs the code of its cell's grid length: 24^3 on all 576 threads,
+// 20^3 on 400 (the rest are twins), and 16^3 on two groups of 256 threads, one
+// target each with its own LDS region (a single target leaves the second group
+// to twins).
 template <int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 fused_batched_kernel(BatchArgs B) {
   static_assert(NT == 576, "the persistent kernel serves grid lengths up to 24");
+  static_assert(2 * fused_lds_elems<16>() <= fused_lds_elems<24>(), "two 16^3 regions must fit");
   __shared__ c64 lds[fused_lds_elems<24>()];
   __shared__ int it_sh;
+  int sq = blockIdx.x % kBatchQueues;  // only thread 0 uses these two
+  int tried = 0;
   for (;;) {
-    if (threadIdx.x == 0) it_sh = atomicAdd(B.counter, 1);
+    if (threadIdx.x == 0) {
+      int it = -1;
+      while (tried < kBatchQueues) {
+        const int idx = atomicAdd(&B.counters[sq], 1);
+        if (idx < B.qlen[sq]) {
+          it = B.qoff[sq] + idx;
+          break;
+        }
+        ++tried;
+        sq = (sq + 1) % kBatchQueues;
+      }
+      it_sh = it;
+    }
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(it_sh);
     __syncthreads();
-    if (it >= B.total) return;
-    const int cell = __builtin_amdgcn_readfirstlane(B.queue[2 * it]);
-    const int item = __builtin_amdgcn_readfirstlane(B.queue[2 * it + 1]);
+    if (it < 0) return;
+    const int cell = __builtin_amdgcn_readfirstlane(B.queue[3 * it]);
+    const int item = __builtin_amdgcn_readfirstlane(B.queue[3 * it + 1]);
+    const int item2 = __builtin_amdgcn_readfirstlane(B.queue[3 * it + 2]);
     const FusedArgs& a = B.cells[cell];
+    const int tr = threadIdx.x;
     switch (a.n) {
-      case 16: fused_item<16, NT>(a, item, blockIdx.x, lds); break;
-      case 20: fused_item<20, NT>(a, item, blockIdx.x, lds); break;
-      default: fused_item<24, NT>(a, item, blockIdx.x, lds); break;
+      case 16: {
+        const int g = tr / 256;  // groups are whole waves
+        const bool second = item2 >= 0 && g == 1;
+        fused_item<16>(a, second ? item2 : item, blockIdx.x, second ? lds + fused_lds_elems<16>() : lds, tr % 256,
+                       !(g == 0 || second));
+        break;
+      }
+      case 20: fused_item<20>(a, item, blockIdx.x, lds, tr % 400, tr >= 400); break;
+      default: fused_item<24>(a, item, blockIdx.x, lds, tr, false); break;
     }
   }
 }
 
-__global__ void reset_counter_kernel(int* c) { *c = 0; }
+__global__ void reset_counters_kernel(int* c, int n) {
+  for (int i = 0; i < n; ++i) c[i] = 0;
+}
 
 template <int N, int WPE>
 hipError_t launch_n(const FusedArgs& a, hipStream_t st) {
@@ -392,7 +421,7 @@ hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int var
 int batched_threads(int nmax) { return nmax > 24 ? 0 : 576; }
 
 hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipStream_t st) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, b.counter);
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(1), 0, st, b.counters, kBatchQueues);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nthreads != 576) return hipErrorInvalidValue;

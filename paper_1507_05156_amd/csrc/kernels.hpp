@@ -58,14 +58,18 @@ hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int var
 int fused_variants(int n);
 size_t fused_acc_scratch_elems(int n, int nslots);  // c64 elements needed in accs (0 if registers)
 
-// Persistent launch over several cells: nwg workgroups of nthreads pop items
-// (queue[2i] = cell, queue[2i+1] = target item) until `total` are taken.
+// Persistent launch over several cells: nwg workgroups of nthreads pop entries
+// (queue[3i] = cell, queue[3i+1] = target item, queue[3i+2] = a second target
+// of the same 16^3 cell or -1) from kBatchQueues sub-queues; sub-queue x holds
+// entries [qoff[x], qoff[x] + qlen[x]) and is counted by counters[x].
 constexpr int kMaxBatchCells = 8;
+constexpr int kBatchQueues = 8;  // one per XCD
 struct BatchArgs {
   FusedArgs cells[kMaxBatchCells];
   const int* queue;
-  int* counter;
-  int total;
+  int* counters;
+  int qoff[kBatchQueues];
+  int qlen[kBatchQueues];
 };
 int batched_threads(int nmax);  // workgroup size for a batch whose largest grid length is nmax (0: none)
 hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipStream_t st);

@@ -49,12 +49,12 @@ struct Cell {
 struct BatchState {
   std::vector<const void*> key;  // u, phi, vphi pointers and nphi of every cell
   DevBuf shadow_u[kMaxBatchCells], shadow_x[kMaxBatchCells], comp[kMaxBatchCells];
-  DevBuf accs, queue, counter;
+  DevBuf accs, queue, counters;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   BatchArgs args{};
-  int nthreads = 0, nwg = 0, total = 0;
+  int nthreads = 0, nwg = 0, entries = 0;
   bool ready = false;
   void reset_graph();
   void release();

@@ -20,11 +20,14 @@ def to_dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
 
 
-def cells_small(with32=False):
+def cells_small(with32=False, odd16=False):
     cell = synth.cubic_cell()
     spec = [(24, (2, 1, 1), 2), (16, (2, 2, 1), 3), (20, (3, 1, 1), 2)]
     if with32:
         spec = [(32, (2, 1, 1), 2), (16, (2, 1, 1), 2)]
+    if odd16:
+        # 9 targets of 16^3 (two per entry: the last entry has one), 7 of 16^3 in another cell
+        spec = [(16, (3, 1, 1), 3), (20, (2, 1, 1), 2), (16, (7, 1, 1), 1)]
     out = []
     for ci, (n, mesh, nb) in enumerate(spec):
         kp = synth.gamma_mesh(mesh[0], cell, mesh[1], mesh[2])
@@ -37,12 +40,13 @@ def rel(x, y):
     return float(np.linalg.norm(x - y) / np.linalg.norm(y))
 
 
-@pytest.mark.parametrize("with32", [False, True])
-def test_batched_matches_per_cell_and_oracle(device, with32):
-    """with32: a plan holding a 32^3 cell runs its cells one after another."""
-    print(f"[gpu] batched with32={with32}", flush=True)
+@pytest.mark.parametrize("with32,odd16", [(False, False), (True, False), (False, True)])
+def test_batched_matches_per_cell_and_oracle(device, with32, odd16):
+    """with32: a plan holding a 32^3 cell runs its cells one after another.
+    odd16: 16^3 cells whose target counts leave a single target in an entry."""
+    print(f"[gpu] batched with32={with32} odd16={odd16}", flush=True)
     from paper_1507_05156_amd.api import Plan
-    cs = cells_small(with32)
+    cs = cells_small(with32, odd16)
     plan = Plan([{k: v for k, v in c.items() if k != "u"} for c in cs], prec="fp32")
     us = [to_dev(c["u"]) for c in cs]
     outs = plan.apply_batched(us)
@@ -112,3 +116,26 @@ def test_autotuner_writes_and_reuses_cache(device, tmp_path):
         got2 = plan2.apply(ud).cpu().numpy()     # cached choice, no new measurement
         assert rel(got2, ref) < tol
         assert os.path.getmtime(path) == mtime
+
+
+def test_batched_autotuner_writes_and_reuses_cache(device, tmp_path):
+    """The first batched call measures the persistent workgroups per CU and stores the choice."""
+    print("[gpu] batched autotuner", flush=True)
+    from paper_1507_05156_amd.api import Plan
+    path = str(tmp_path / "tune.json")
+    cs = cells_small()
+    descs = [{k: v for k, v in c.items() if k != "u"} for c in cs]
+    us = [to_dev(c["u"]) for c in cs]
+    ref = [Plan(d, prec="fp32").apply(u) for d, u in zip(descs, us)]
+    plan = Plan(descs, prec="fp32", tune_cache=path)
+    outs = plan.apply_batched(us)
+    data = json.load(open(path))
+    keys = [k for k in data if "/batched/" in k]
+    assert keys and data[keys[0]]["wg_per_cu"] in (1, 2), data
+    mtime = os.path.getmtime(path)
+    plan2 = Plan(descs, prec="fp32", tune_cache=path)
+    outs2 = plan2.apply_batched(us)
+    assert os.path.getmtime(path) == mtime
+    for o, o2, r in zip(outs, outs2, ref):
+        assert rel(o.cpu().numpy(), r.cpu().numpy()) < 1e-6
+        assert rel(o2.cpu().numpy(), r.cpu().numpy()) < 1e-6
