@@ -280,6 +280,37 @@ def step_matfree(psi, kpts, a, omega, avec, dt, alpha, vloc=None, order=4):
     return acc
 
 
+def step_rows(psi, kpts, a, omega, avec, dt, alpha, rows, vloc=None, order=4):
+    """The Taylor step of Eqs. (9)-(10) for the listed orbitals (k, i) only.
+
+    Once V_x is built from psi(t_n), h acts on each orbital by itself: the
+    kinetic term on its own k, v_loc pointwise, V_x through the pair sum over
+    all occupied (k', j). So the terms phi_m = (-i dt/m) h phi_{m-1} of one
+    orbital need that orbital alone. Returns {(k, i): psi_ki(t_n + dt)}.
+    """
+    from .fock import general_apply
+    psi = np.asarray(psi, dtype=np.complex128)
+    kpts = np.asarray(kpts, dtype=np.float64).reshape(-1, 3)
+    nk = psi.shape[0]
+    n = psi.shape[-3:]
+    out = {}
+    for k, i in rows:
+        term = psi[k, i].copy()
+        acc = term.copy()
+        for m in range(1, order + 1):
+            y = kinetic_apply(term[None, None], kpts[k:k + 1], a, avec)[0, 0]
+            if vloc is not None:
+                y = y + np.asarray(vloc).reshape(n) * term
+            if alpha != 0.0:
+                X = np.zeros((nk, 1) + tuple(n), dtype=np.complex128)
+                X[k, 0] = term
+                y = y + alpha * general_apply(X, psi, psi, kpts, a, omega, rows=[(k, 0)])[k, 0]
+            term = (-1j * dt / m) * y
+            acc = acc + term
+        out[(k, i)] = acc
+    return out
+
+
 def step_tangent_matfree(psi, dpsi, davec, kpts, a, omega, avec, dt, alpha, vloc=None, order=4):
     """Forward-mode derivative of step_matfree along (dpsi, davec)."""
     from .fock import general_apply

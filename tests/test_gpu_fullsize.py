@@ -1,0 +1,134 @@
+"""Parity at the full sizes of the named workloads, in the launch configurations
+bench.py times, on outputs the FP64 oracle evaluates one by one.
+
+* 32^3 grid, 6^3 k, 16 bands, FP32 form (the bench workload): sampled output rows,
+  each a sum over all 3,456 source orbitals.
+* Three uneven cells in one persistent launch: one sampled row per cell.
+* 24^3 grid, 4^3 k, 16 bands, FP64: one Taylor-4 step, sampled rows.
+* The same cell through 20 checkpointed steps: dE_ex/dA0 by the adjoint against
+  central finite differences (about 8 minutes of GPU time: run with
+  FOCKMI_RUN_SLOW=1).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import taylor as otaylor
+from paper_1507_05156_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+OMEGA = synth.OMEGA_HSE
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def row_err(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def test_bench_workload_fp32_sampled_rows(device):
+    """32^3 / 216 k / 16 bands through the fused FP32 kernel, as bench.py runs it."""
+    print("[gpu] full size 32^3 fp32 rows", flush=True)
+    from paper_1507_05156_amd.api import Plan
+    cell, kp, u = synth.workload(2)
+    plan = Plan(dict(n=32, a=cell, kpts=kp, nb=16, omega=OMEGA), prec="fp32")
+    got = plan.apply(to_dev(u)).cpu().numpy()
+    rows = [(0, 0), (215, 15)]
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA, rows=rows)
+    for k, i in rows:
+        e = row_err(got[k, i], ref[k, i])
+        print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
+        assert e < 1e-6, (k, i, e)
+
+
+def test_batched_workload_sampled_rows(device):
+    """16^3/27 k/8 b, 20^3/64 k/12 b and 24^3/125 k/16 b in one persistent launch."""
+    print("[gpu] full size batched rows", flush=True)
+    from paper_1507_05156_amd.api import Plan
+    cells, us = [], []
+    for ci in range(3):
+        a, kp, u = synth.workload(4, ci)
+        cells.append(dict(n=u.shape[2], a=a, kpts=kp, nb=u.shape[1], omega=OMEGA))
+        us.append(u)
+    plan = Plan(cells, prec="fp32")
+    outs = plan.apply_batched([to_dev(u) for u in us])
+    for ci, (c, u) in enumerate(zip(cells, us)):
+        k, i = c["kpts"].shape[0] - 1, c["nb"] // 2
+        ref = oracle.fock_apply(u, u, c["kpts"], c["a"], OMEGA, rows=[(k, i)])[k, i]
+        e = row_err(outs[ci][k, i].cpu().numpy(), ref)
+        print(f"  cell {ci} row {(k, i)}: rel err {e:.3e}", flush=True)
+        assert e < 1e-6, (ci, e)
+
+
+def test_differentiation_workload_taylor_step_rows(device):
+    """One FP64 Taylor-4 step at 24^3 / 64 k / 16 bands with a field and alpha = 1/4."""
+    print("[gpu] full size 24^3 taylor rows", flush=True)
+    from paper_1507_05156_amd.api import Plan
+    cell, kp, u = synth.workload(3)
+    plan = Plan(dict(n=24, a=cell, kpts=kp, nb=16, omega=OMEGA), prec="fp64")
+    avec = np.array([0.0, 0.0, 0.03])
+    psi = to_dev(u)
+    plan.taylor_step(psi, avec, 0.02, 0.25)
+    got = psi.cpu().numpy()
+    rows = [(5, 3), (63, 15)]
+    ref = otaylor.step_rows(u, kp, cell, OMEGA, avec, 0.02, 0.25, rows)
+    for (k, i), r in ref.items():
+        e = row_err(got[k, i], r)
+        print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
+        assert e < 1e-10, (k, i, e)
+
+
+class _Progress:
+    """Delegates to a Plan and prints a line per Taylor step and per adjoint step, so
+    that a long propagation shows it is moving."""
+
+    def __init__(self, plan):
+        self._plan = plan
+        self.fwd = 0
+        self.bwd = 0
+
+    def __getattr__(self, name):
+        return getattr(self._plan, name)
+
+    def taylor_step(self, *a, **k):
+        self.fwd += 1
+        print(f"  taylor step {self.fwd}", flush=True)
+        return self._plan.taylor_step(*a, **k)
+
+    def taylor_step_vjp(self, *a, **k):
+        self.bwd += 1
+        print(f"  adjoint step {self.bwd}", flush=True)
+        return self._plan.taylor_step_vjp(*a, **k)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("FOCKMI_RUN_SLOW") != "1", reason="about 8 minutes of GPU time; FOCKMI_RUN_SLOW=1")
+def test_differentiation_workload_a0_gradient_fd(device):
+    """dE_ex/dA0 through 20 Taylor-4 steps (dt = 0.02, sin^2 pulse, 1.55 eV, A0 = 0.05,
+    checkpoints every 5 steps) at 24^3 / 64 k / 16 bands: adjoint vs central FD, h = 1e-5."""
+    print("[gpu] full size 24^3 A0 gradient", flush=True)
+    import torch
+    from paper_1507_05156_amd import autograd as ag
+    from paper_1507_05156_amd.api import Plan
+    cell, kp, u = synth.workload(3)
+    plan = _Progress(Plan(dict(n=24, a=cell, kpts=kp, nb=16, omega=OMEGA), prec="fp64"))
+    kw = dict(nsteps=20, dt=0.02, alpha=0.25, omega_l=0.0569614, checkpoint_every=5)
+    A0 = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    _, eex = ag.propagate(plan, to_dev(u), A0, **kw)
+    eex.backward()
+    ad = float(A0.grad)
+    h = 1e-5
+    with torch.no_grad():
+        ep = float(ag.propagate(plan, to_dev(u), torch.tensor(0.05 + h, dtype=torch.float64), **kw)[1])
+        em = float(ag.propagate(plan, to_dev(u), torch.tensor(0.05 - h, dtype=torch.float64), **kw)[1])
+    fd = (ep - em) / (2 * h)
+    print(f"  E_ex = {float(eex.detach()):.12e}, adjoint {ad:.12e}, FD {fd:.12e}, rel {abs(fd - ad) / abs(ad):.3e}",
+          flush=True)
+    assert abs(fd - ad) / abs(ad) < 1e-6

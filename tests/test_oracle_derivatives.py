@@ -205,3 +205,16 @@ def test_energy_matfree_matches_dense_and_fd():
         da[ax] = 1.0
         fd = (f(u, avec + h * da) - f(u, avec - h * da)) / (2 * h)
         assert abs(fd - ga[ax]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_step_rows_matches_full_step():
+    """The single-orbital Taylor step equals the rows of the full step (v_loc and V_x on)."""
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(16, cell, kp, 2, seed=71)
+    vloc = 0.1 * np.cos(2 * np.pi * np.arange(16 ** 3) / 16 ** 3)
+    av = np.array([0.0, 0.01, 0.02])
+    full = otaylor.step_matfree(u, kp, cell, OMEGA, av, 0.05, 0.25, vloc=vloc)
+    rows = otaylor.step_rows(u, kp, cell, OMEGA, av, 0.05, 0.25, [(1, 0), (0, 1)], vloc=vloc)
+    for (k, i), r in rows.items():
+        assert np.linalg.norm(r - full[k, i]) < 1e-13 * np.linalg.norm(full[k, i])
