@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
 # the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "08ccaa81b78e209a9e68421edffa903fce8d45e684172a6a1dc41e15faf594c1",
+    "sources_sha256": "68e81e2a24eafc071ad874026abc90ccc97e2a98ae65c168652834296944a86d",
     "workload": 2,
-    "fetch_kib": 6144664350.5, "write_kib": 3963010410.625,
+    "fetch_kib": 6436736371.6875, "write_kib": 3773182410.0,
     "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
 }
 KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/fft_reg.hpp",

@@ -179,7 +179,7 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
     return s;
   }
   const int nitems = c.nk * nx;
-  if ((s = comp.ensure((size_t)nitems * nr * sizeof(c128), workspace_cap, "compensation buffer")) != FOCK_OK)
+  if ((s = comp.ensure((size_t)nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
     return s;
   const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, nitems);
   if (acc_elems && (s = accs.ensure(acc_elems * sizeof(c64), workspace_cap, "FP32 partial sums")) != FOCK_OK)
@@ -191,7 +191,7 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
   a.Kt = (const float*)c.Kt.ptr;
   a.qidx = (const int*)c.qidx.ptr;
   a.out = out;
-  a.comp = (c128*)comp.ptr;
+  a.comp = (c64*)comp.ptr;
   a.accs = (c64*)accs.ptr;
   a.nk = c.nk;
   a.nx = nx;

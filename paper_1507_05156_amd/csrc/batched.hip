@@ -125,7 +125,7 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
       if (phi[ci] != u[ci] &&
           (s = B.shadow_x[ci].ensure(nx * sizeof(c64), workspace_cap, "batched shadow (phi)")) != FOCK_OK)
         return s;
-      if ((s = B.comp[ci].ensure(nx * sizeof(c128), workspace_cap, "batched compensation")) != FOCK_OK) return s;
+      if ((s = B.comp[ci].ensure(nx * sizeof(c64), workspace_cap, "batched compensation")) != FOCK_OK) return s;
     }
     if (acc_slots_needed &&
         (s = B.accs.ensure(fused_acc_scratch_elems(32, (int)acc_slots_needed) * sizeof(c64), workspace_cap,
@@ -145,7 +145,7 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
       a.Kt = (const float*)c.Kt.ptr;
       a.qidx = (const int*)c.qidx.ptr;
       a.out = (c128*)vphi[ci];
-      a.comp = (c128*)B.comp[ci].ptr;
+      a.comp = (c64*)B.comp[ci].ptr;
       a.accs = (c64*)B.accs.ptr;
       a.nk = c.nk;
       a.nx = nphi[ci];

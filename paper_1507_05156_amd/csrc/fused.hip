@@ -135,6 +135,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   // table and FP32 partial sums are value-major: (v, t) at (v * NTI + t) * size
   const unsigned voff_x = (unsigned)((chi * N + clo) * 8);
   const unsigned voff_f = twin ? 0xF0000000u : 2u * voff_x;  // FP64 stores of twins are dropped
+  const unsigned voff_c = twin ? 0xF0000000u : voff_x;        // so are their compensation stores
   const unsigned voff_t4 = (unsigned)(t * 4);
   const unsigned voff_t8 = (unsigned)(t * 8);
   constexpr unsigned FB64 = NR * 8u;  // bytes of one complex64 field
@@ -142,7 +143,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
 
   const rsrc_t rX = make_rsrc(a.X + ((long)kt * a.nx + s) * NR, FB64);
   const rsrc_t rOut = make_rsrc(a.out + ((long)kt * a.nx + s) * NR, FB128);
-  const rsrc_t rComp = make_rsrc(a.comp + ((long)kt * a.nx + s) * NR, FB128);
+  const rsrc_t rComp = make_rsrc(a.comp + ((long)kt * a.nx + s) * NR, FB64);
   const rsrc_t rAcc = make_rsrc(ACCREG ? a.X : a.accs + (long)acc_slot * NR, ACCREG ? 0u : FB64);
 
   c64 acc[ACCREG ? N : 1];
@@ -297,7 +298,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
             si = o.im;
           }
           if (!first_ks) {
-            const c128 c = ld_c128(rComp, voff_f, so);
+            const c64 c = ld_c64(rComp, voff_c, so / 2);
             cr = c.re;
             ci = c.im;
           }
@@ -307,7 +308,8 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
             st_c128(c128{sr + cr, si + ci}, rOut, voff_f, so);
           } else {
             st_c128(c128{sr, si}, rOut, voff_f, so);
-            st_c128(c128{cr, ci}, rComp, voff_f, so);
+            // the compensation is a rounding-error term (~1e-16 |s|): FP32 keeps it
+            st_c64(c64{(float)cr, (float)ci}, rComp, voff_c, so / 2);
           }
         }
       }

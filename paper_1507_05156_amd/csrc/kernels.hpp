@@ -44,7 +44,7 @@ struct FusedArgs {
   const float* Kt;    // [nq][nr] fused layout, 1/N_r folded
   const int* qidx;    // [nk][nk] table of (target k, source k')
   c128* out;          // [nk][nx][nr] FP64 result (running sum)
-  c128* comp;         // [nk][nx][nr] FP64 Neumaier compensation
+  c64* comp;          // [nk][nx][nr] Neumaier compensation of out, rounded to FP32
   c64* accs;          // per-workgroup FP32 partial sums when they do not fit in registers
   int nk, nx, nb;
   int item0, nitems;  // work items [item0, item0 + nitems) of nk*nx
