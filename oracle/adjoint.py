@@ -15,7 +15,8 @@ For y = V_x[u] phi with cotangent g (the gradient of L with respect to y):
 
   where W(rho) = (1/N_r) IDFT(K_{k'-k} DFT(rho)). Both families are the
   general operator with the target set to u and the roles of the other two
-  arrays swapped.
+  arrays swapped. With down-sampling, k' runs over the source sub-mesh only
+  and 1/N_k becomes 1/|S|.
 
 For E_x = (g_s/2)(1/N_k)(Omega/N_r) sum conj(u) V_x[u] u (real for exact
 arithmetic): grad_u E_x = 2 (g_s/N_k)(Omega/N_r) V_x[u] u.
@@ -27,10 +28,22 @@ from .fock import general_apply, fock_apply
 from .lattice import volume
 
 
-def fock_vjp(u, phi, g, kpts, a, omega):
-    """(g_u, g_phi) for y = V_x[u] phi and cotangent g of y."""
-    g_phi = general_apply(g, u, u, kpts, a, omega)
-    g_u = general_apply(u, phi, g, kpts, a, omega) + general_apply(u, g, phi, kpts, a, omega)
+def fock_vjp(u, phi, g, kpts, a, omega, src=None):
+    """(g_u, g_phi) for y = V_x[u] phi and cotangent g of y.
+
+    With a down-sampled source set src (weight 1/|src|), u enters only through
+    the source k-points: g_u is zero elsewhere, and on a source k' it sums over
+    every target k with the same weight.
+    """
+    u = np.asarray(u, dtype=np.complex128)
+    nk = u.shape[0]
+    src = list(range(nk)) if src is None else [int(x) for x in src]
+    w = -1.0 / len(src)
+    g_phi = general_apply(g, u, u, kpts, a, omega, src=src)
+    g_u = np.zeros_like(u)
+    us = u[src]
+    g_u[src] = (general_apply(us, phi, g, kpts, a, omega, tgt=src, weight=w)
+                + general_apply(us, g, phi, kpts, a, omega, tgt=src, weight=w))
     return g_u, g_phi
 
 

@@ -259,28 +259,28 @@ def kinetic_dapply(x, kpts, a, avec, axis):
     return out
 
 
-def h_apply(u, x, kpts, a, omega, avec, alpha, vloc=None):
-    """h x with h = T[a] + v_loc + alpha V_x[u]."""
+def h_apply(u, x, kpts, a, omega, avec, alpha, vloc=None, src=None):
+    """h x with h = T[a] + v_loc + alpha V_x[u] (V_x over the source sub-mesh src)."""
     from .fock import fock_apply
     y = kinetic_apply(x, kpts, a, avec)
     if vloc is not None:
         y = y + np.asarray(vloc).reshape(x.shape[-3:]) * x
     if alpha != 0.0:
-        y = y + alpha * fock_apply(u, x, kpts, a, omega)
+        y = y + alpha * fock_apply(u, x, kpts, a, omega, src=src)
     return y
 
 
-def step_matfree(psi, kpts, a, omega, avec, dt, alpha, vloc=None, order=4):
+def step_matfree(psi, kpts, a, omega, avec, dt, alpha, vloc=None, order=4, src=None):
     psi = np.asarray(psi, dtype=np.complex128)
     term = psi.copy()
     acc = psi.copy()
     for m in range(1, order + 1):
-        term = (-1j * dt / m) * h_apply(psi, term, kpts, a, omega, avec, alpha, vloc)
+        term = (-1j * dt / m) * h_apply(psi, term, kpts, a, omega, avec, alpha, vloc, src=src)
         acc = acc + term
     return acc
 
 
-def step_rows(psi, kpts, a, omega, avec, dt, alpha, rows, vloc=None, order=4):
+def step_rows(psi, kpts, a, omega, avec, dt, alpha, rows, vloc=None, order=4, src=None):
     """The Taylor step of Eqs. (9)-(10) for the listed orbitals (k, i) only.
 
     Once V_x is built from psi(t_n), h acts on each orbital by itself: the
@@ -304,7 +304,7 @@ def step_rows(psi, kpts, a, omega, avec, dt, alpha, rows, vloc=None, order=4):
             if alpha != 0.0:
                 X = np.zeros((nk, 1) + tuple(n), dtype=np.complex128)
                 X[k, 0] = term
-                y = y + alpha * general_apply(X, psi, psi, kpts, a, omega, rows=[(k, 0)])[k, 0]
+                y = y + alpha * general_apply(X, psi, psi, kpts, a, omega, rows=[(k, 0)], src=src)[k, 0]
             term = (-1j * dt / m) * y
             acc = acc + term
         out[(k, i)] = acc
