@@ -63,20 +63,30 @@ typedef struct {
   int nb;                /* occupied bands per k-point (all fully occupied) */
   double omega;          /* screening parameter w (bohr^-1), > 0 */
   double gs;             /* spin degeneracy used by fock_energy (2 = closed shell) */
+  /* Down-sampling (Sec. II C, after Eq. (16)): the sum over occupied orbitals
+   * runs over the k-points of a sub-mesh S only, with weight 1/|S| in place
+   * of 1/N_k (the paper samples 4^3 q-points for a 12^3 k-mesh). Every
+   * orbital array still holds all nk k-points; u_occ enters only at S.
+   * nsrc = 0 (or src = NULL) means S = every k-point. */
+  int nsrc;              /* |S|, 0 <= nsrc <= nk */
+  const int* src;        /* HOST [nsrc] distinct indices into kpts; copied at plan creation */
 } fock_cell_desc;
 
 /* Creates a plan for ncells cells on the current HIP device. Builds the kernel
  * tables K_q for every distinct q = k_i - k_j of each cell (FP64 on the GPU;
  * FP32 copies for FOCK_FP32_COMP). tune_cache_json may be NULL; otherwise it
  * is a path to the autotuner's JSON cache (read, and written after tuning).
- * Errors: FOCK_ERR_ARG, FOCK_ERR_SIZE, FOCK_ERR_HIP, FOCK_ERR_NOMEM. */
+ * Errors: FOCK_ERR_ARG (also for a source set with repeated or out-of-range
+ * indices), FOCK_ERR_SIZE, FOCK_ERR_HIP, FOCK_ERR_NOMEM. */
 fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec prec,
                              const char* tune_cache_json, fockmi_plan* out);
 
 /* Frees everything the plan owns (never caller memory). NULL is accepted. */
 fock_status fock_plan_destroy(fockmi_plan plan);
 
-/* Eqs. (15)-(16): vphi[k][p] = (V_x[u_occ] phi)[k][p] for p < nphi.
+/* Eqs. (15)-(16): vphi[k][p] = (V_x[u_occ] phi)[k][p] for p < nphi, the sum
+ * running over the source k-points S of the cell (all k unless down-sampled)
+ * with weight 1/|S|.
  *   u_occ : device [nk][nb][N_r] complex128, occupied orbitals
  *   phi   : device [nk][nphi][N_r] complex128 target fields (may equal u_occ)
  *   vphi  : device [nk][nphi][N_r] complex128 output, overwritten; must not
@@ -94,9 +104,9 @@ fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* e
 /* Reverse mode of fock_apply (derived from Eq. (15)). Given the cotangent
  * g_vphi of vphi (PyTorch convention: dL/dRe + i dL/dIm), writes
  *   g_phi[k][p] = (V_x[u] g)[k][p]                       (device [nk][nphi][N_r], may be NULL)
- *   g_u[k'][j]  = -(1/N_k) sum_{k,i} ( g_ik * W_{k'-k}(conj(phi_ik) u_jk')
- *                                    + phi_ik * W_{k'-k}(conj(g_ik) u_jk') )
- *                                                          (device [nk][nb][N_r], may be NULL)
+ *   g_u[k'][j]  = -(1/|S|) sum_{k,i} ( g_ik * W_{k'-k}(conj(phi_ik) u_jk')
+ *                                    + phi_ik * W_{k'-k}(conj(g_ik) u_jk') )   for k' in S,
+ *                 0 for k' outside S                      (device [nk][nb][N_r], may be NULL)
  * Outputs are overwritten and must not overlap the inputs. Stream-ordered. */
 fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
                      const void* g_vphi, void* g_u_occ, void* g_phi, void* stream);
@@ -115,7 +125,8 @@ fock_status taylor_step(fockmi_plan plan, int cell, void* psi, const double* vlo
                         double dt, double alpha, int order, double* max_norm_dev, void* stream);
 
 /* Reverse mode of taylor_step for the same arguments (psi_n is the state
- * BEFORE the step). Given g_next, the cotangent of psi(t_n + dt):
+ * BEFORE the step); not available for a down-sampled cell (FOCK_ERR_ARG).
+ * Given g_next, the cotangent of psi(t_n + dt):
  *   g_psi  : device [nk][nb][N_r] complex128 <- cotangent of psi(t_n), overwritten
  *   g_a    : host [3] <- d L / d (A/c) of this step (added to nothing; overwritten)
  * Stream-ordered, synchronises to return g_a. */
@@ -124,7 +135,8 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
                             const void* g_next, void* g_psi, double g_a[3], void* stream);
 
 /* Energy functional of the propagated state (Eq. (22) restricted to the
- * pieces built here; E_GS is left to the caller):
+ * pieces built here; E_GS is left to the caller); not available for a
+ * down-sampled cell (FOCK_ERR_ARG):
  *   E = (g_s/N_k)(Omega/N_r) sum conj(psi) (T[A/c] + v_loc) psi + alpha * E_x[psi]
  *   *e_out    (host)   <- E
  *   grad_psi  (device [nk][nb][N_r] complex128, may be NULL) <- dE/dpsi in the
@@ -140,10 +152,10 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
 fock_status fock_orthonormalize(fockmi_plan plan, int cell, void* psi, void* stream);
 
 /* All cells of the plan in one persistent launch (FOCK_FP32_COMP plans with up
- * to 8 cells of grid lengths 16, 20, 24), replayed from a captured hipGraph
- * while the same buffers are passed: u_occ[c], phi[c], vphi[c] as in
- * fock_apply for cell c, nphi[c] targets. Host arrays of device pointers, one
- * entry per cell. Other plans run their cells one after another.
+ * to 8 cells of grid lengths 16, 20, 24, none down-sampled), replayed from a
+ * captured hipGraph while the same buffers are passed: u_occ[c], phi[c],
+ * vphi[c] as in fock_apply for cell c, nphi[c] targets. Host arrays of device
+ * pointers, one entry per cell. Other plans run their cells one after another.
  * Stream-ordered. */
 fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
                                const int* nphi, void* const* vphi, void* stream);

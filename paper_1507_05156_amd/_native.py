@@ -32,7 +32,8 @@ EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_energy",
 
 class CellDesc(C.Structure):
     _fields_ = [("n", C.c_int * 3), ("a", (C.c_double * 3) * 3), ("nk", C.c_int),
-                ("kpts", C.POINTER(C.c_double)), ("nb", C.c_int), ("omega", C.c_double), ("gs", C.c_double)]
+                ("kpts", C.POINTER(C.c_double)), ("nb", C.c_int), ("omega", C.c_double), ("gs", C.c_double),
+                ("nsrc", C.c_int), ("src", C.POINTER(C.c_int))]
 
 
 class FockError(RuntimeError):

@@ -29,7 +29,8 @@ class Plan:
     """A set of cells (grid, lattice, k-points, bands, screening) prepared on one GPU.
 
     cells : list of dicts with keys n (int or 3-tuple), a (3x3 rows), kpts ([nk][3]),
-            nb, omega, gs (default 2.0)
+            nb, omega, gs (default 2.0), and optionally src: the k indices of a
+            down-sampled source sub-mesh (the pair sum runs over them with weight 1/len(src))
     prec  : "fp64" (plain staged FP64 path) or "fp32" (fused complex64 pair FFTs with
             compensated FP64 accumulation)
     """
@@ -58,9 +59,16 @@ class Plan:
             d.nb = int(c["nb"])
             d.omega = float(c["omega"])
             d.gs = float(c.get("gs", 2.0))
+            src = c.get("src")
+            if src is not None:
+                src = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1))
+                self._keep.append(src)
+                d.nsrc = len(src)
+                d.src = src.ctypes.data_as(C.POINTER(C.c_int))
             self.cells.append(dict(n=n, a=a, kpts=kpts, nk=len(kpts), nb=int(c["nb"]), omega=float(c["omega"]),
                                    gs=float(c.get("gs", 2.0)), nr=n[0] * n[1] * n[2],
-                                   vol=abs(float(np.linalg.det(a)))))
+                                   vol=abs(float(np.linalg.det(a))),
+                                   src=None if src is None else [int(x) for x in src]))
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = C.c_void_p()
         path = tune_cache.encode() if tune_cache else None

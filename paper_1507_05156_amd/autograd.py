@@ -49,9 +49,15 @@ class FockEnergy(torch.autograd.Function):
     def backward(ctx, g):
         (u,) = ctx.saved_tensors
         c = ctx.plan.cells[ctx.cell]
+        w = (c["gs"] / 2.0) / c["nk"] * c["vol"] / c["nr"]
         v = ctx.plan.apply(u, None, ctx.cell)
-        w = 2.0 * c["gs"] / c["nk"] * c["vol"] / c["nr"]
-        return v * (w * float(g)), None, None
+        if c.get("src") is None:
+            # V_x Hermitian and symmetric in its two occurrences of u: grad = 4 w V_x u
+            return v * (4.0 * w * float(g)), None, None
+        # down-sampled: 2 w V_x u from the targets, plus the adjoint through the
+        # source orbitals with cotangent w u
+        gu, _ = ctx.plan.vjp(u, u, u * w, ctx.cell, need_u=True, need_phi=False)
+        return (v * (2.0 * w) + gu) * float(g), None, None
 
 
 class TaylorStep(torch.autograd.Function):

@@ -75,16 +75,18 @@ fock_status Plan::check_ready(int cell) const {
 }
 
 // ------------------------------------------------------------------ plumbing
-static fock_status plain_pipeline(Plan& pl, Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns,
-                                  c128* out, double scale, bool accumulate, hipStream_t st, size_t cap);
+static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P,
+                                  const c128* M, int ns, c128* out, double scale, bool accumulate, hipStream_t st,
+                                  size_t cap);
 
-fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
-                            double scale, bool accumulate, hipStream_t st) {
-  const std::string key = key_for(c, nx, "plain");
+fock_status Plan::run_plain(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                            c128* out, double scale, bool accumulate, hipStream_t st) {
+  const std::string key = key_for(c, ps, nx, "plain");
   TuneEntry te;
-  if (tune.get(key, &te)) return plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, accumulate, st,
+  if (tune.get(key, &te)) return plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, accumulate, st,
                                                 (size_t)te.fields["batch_mb"] << 20);
-  if (!tuning || accumulate) return plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, accumulate, st, batch_cap);
+  if (!tuning || accumulate)
+    return plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, accumulate, st, batch_cap);
   // measure the pair-batch size (each candidate writes the same result)
   hipEvent_t e0, e1;
   hipError_t e;
@@ -94,7 +96,7 @@ fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const
   int bmb = 1024;
   for (int mb : {256, 1024}) {
     (void)hipEventRecord(e0, st);
-    fock_status s = plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, false, st, (size_t)mb << 20);
+    fock_status s = plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)mb << 20);
     if (s != FOCK_OK) return s;
     (void)hipEventRecord(e1, st);
     if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
@@ -111,15 +113,16 @@ fock_status Plan::run_plain(Cell& c, const c128* X, int nx, const c128* P, const
   te.fields["ms"] = best;
   tune.put(key, te);
   save_tune();
-  return plain_pipeline(*this, c, X, nx, P, M, ns, out, scale, false, st, (size_t)bmb << 20);
+  return plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)bmb << 20);
 }
 
-static fock_status plain_pipeline(Plan& pl, Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns,
-                                  c128* out, double scale, bool accumulate, hipStream_t st, size_t cap) {
+static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P,
+                                  const c128* M, int ns, c128* out, double scale, bool accumulate, hipStream_t st,
+                                  size_t cap) {
   const int nr = c.nr;
   const size_t per_k = (size_t)ns * nx * nr * sizeof(c128);
   int kb = (int)std::max<size_t>(1, cap / std::max<size_t>(per_k, 1));
-  kb = std::min(kb, c.nk);
+  kb = std::min(kb, ps.nsk);
   kb = std::max(1, std::min(kb, 65535 / std::max(1, ns * nx)));  // grid.y of the batch kernels
   if ((long)ns * nx > 65535) return fail(FOCK_ERR_SIZE, "too many band pairs per k-point pair (%d x %d)", ns, nx);
   fock_status s = pl.batch.ensure((size_t)kb * per_k, pl.workspace_cap, "plain-path batch buffer");
@@ -127,17 +130,17 @@ static fock_status plain_pipeline(Plan& pl, Cell& c, const c128* X, int nx, cons
   c128* buf = (c128*)pl.batch.ptr;
   hipError_t e;
   if ((e = pl.prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
-  for (int k = 0; k < c.nk; ++k) {
+  for (int k = 0; k < ps.ntk; ++k) {
     const c128* Xk = X + (size_t)k * nx * nr;
     c128* outk = out + (size_t)k * nx * nr;
-    for (int ks0 = 0; ks0 < c.nk; ks0 += kb) {
-      const int nkb = std::min(kb, c.nk - ks0);
+    for (int ks0 = 0; ks0 < ps.nsk; ks0 += kb) {
+      const int nkb = std::min(kb, ps.nsk - ks0);
       if ((e = launch_pair_product(buf, Xk, P, ks0, nkb, ns, nx, nr, st)) != hipSuccess)
         return hip_fail(e, "pair product");
       if ((e = launch_fft3_plain(buf, nkb * ns * nx, c.geom, -1, st)) != hipSuccess)
         return hip_fail(e, "forward FFT");
-      if ((e = launch_kernel_mul(buf, (const double*)c.K64.ptr, (const int*)c.qidx.ptr, k, c.nk, ks0, nkb, ns * nx,
-                                 nr, st)) != hipSuccess)
+      if ((e = launch_kernel_mul(buf, (const double*)c.K64.ptr, ps.qidx, k, ps.nsk, ks0, nkb, ns * nx, nr, st)) !=
+          hipSuccess)
         return hip_fail(e, "kernel multiply");
       if ((e = launch_fft3_plain(buf, nkb * ns * nx, c.geom, +1, st)) != hipSuccess)
         return hip_fail(e, "inverse FFT");
@@ -160,25 +163,26 @@ fock_status Plan::shadow(DevBuf& buf, const c128* src, size_t count, const char*
   return FOCK_OK;
 }
 
-fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
-                            double scale, bool accumulate, hipStream_t st) {
+fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                            c128* out, double scale, bool accumulate, hipStream_t st) {
   const int nr = c.nr;
   const c64 *Xs = nullptr, *Ps = nullptr, *Ms = nullptr;
   fock_status s;
-  if ((s = shadow(shadow_p, P, (size_t)c.nk * ns * nr, "complex64 shadow (P)", st, &Ps)) != FOCK_OK) return s;
+  if ((s = shadow(shadow_p, P, (size_t)ps.nsk * ns * nr, "complex64 shadow (P)", st, &Ps)) != FOCK_OK) return s;
   if (M == P) {
     Ms = Ps;
-  } else if ((s = shadow(shadow_m, M, (size_t)c.nk * ns * nr, "complex64 shadow (M)", st, &Ms)) != FOCK_OK) {
+  } else if ((s = shadow(shadow_m, M, (size_t)ps.nsk * ns * nr, "complex64 shadow (M)", st, &Ms)) != FOCK_OK) {
     return s;
   }
-  if (X == P && nx == ns) {
+  const bool same_k = ps.ntk == ps.nsk && nx == ns;  // then X may share a source array's shadow
+  if (same_k && X == P) {
     Xs = Ps;
-  } else if (X == M && nx == ns) {
+  } else if (same_k && X == M) {
     Xs = Ms;
-  } else if ((s = shadow(shadow_x, X, (size_t)c.nk * nx * nr, "complex64 shadow (X)", st, &Xs)) != FOCK_OK) {
+  } else if ((s = shadow(shadow_x, X, (size_t)ps.ntk * nx * nr, "complex64 shadow (X)", st, &Xs)) != FOCK_OK) {
     return s;
   }
-  const int nitems = c.nk * nx;
+  const int nitems = ps.ntk * nx;
   if ((s = comp.ensure((size_t)nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
     return s;
   const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, nitems);
@@ -189,11 +193,11 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
   a.P = Ps;
   a.M = Ms;
   a.Kt = (const float*)c.Kt.ptr;
-  a.qidx = (const int*)c.qidx.ptr;
+  a.qidx = ps.qidx;
   a.out = out;
   a.comp = (c64*)comp.ptr;
   a.accs = (c64*)accs.ptr;
-  a.nk = c.nk;
+  a.nk = ps.nsk;
   a.nx = nx;
   a.nb = ns;
   a.item0 = 0;
@@ -204,7 +208,7 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
   a.n = c.geom.n1;
   int variant = 0;
   hipError_t e;
-  const std::string key = key_for(c, nx, "fused");
+  const std::string key = key_for(c, ps, nx, "fused");
   TuneEntry te;
   if (tune.get(key, &te)) {
     variant = (int)te.fields["variant"];
@@ -249,10 +253,11 @@ fock_status Plan::run_fused(Cell& c, const c128* X, int nx, const c128* P, const
   return FOCK_OK;
 }
 
-std::string Plan::key_for(const Cell& c, int nx, const char* what) const {
-  char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s/%s/%s/n%dx%dx%d/nk%d/nb%d/nx%d", arch_name().c_str(),
-                prec == FOCK_FP32_COMP ? "fp32" : "fp64", what, c.geom.n1, c.geom.n2, c.geom.n3, c.nk, c.nb, nx);
+std::string Plan::key_for(const Cell& c, const PairSet& ps, int nx, const char* what) const {
+  char buf[192];
+  std::snprintf(buf, sizeof(buf), "%s/%s/%s/n%dx%dx%d/nt%d/ns%d/nb%d/nx%d", arch_name().c_str(),
+                prec == FOCK_FP32_COMP ? "fp32" : "fp64", what, c.geom.n1, c.geom.n2, c.geom.n3, ps.ntk, ps.nsk, c.nb,
+                nx);
   return buf;
 }
 
@@ -260,10 +265,34 @@ void Plan::save_tune() {
   if (!tune_path.empty()) (void)tune.save(tune_path);
 }
 
-fock_status Plan::general(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
-                          double scale, bool accumulate, hipStream_t st) {
-  if (prec == FOCK_FP32_COMP) return run_fused(c, X, nx, P, M, ns, out, scale, accumulate, st);
-  return run_plain(c, X, nx, P, M, ns, out, scale, accumulate, st);
+fock_status Plan::general(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                          c128* out, double scale, bool accumulate, hipStream_t st) {
+  if (prec == FOCK_FP32_COMP) return run_fused(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
+  return run_plain(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
+}
+
+fock_status Plan::sources(Cell& c, const c128* arr, int nper, DevBuf& buf, hipStream_t st, const c128** out) {
+  if (!c.ds) {
+    *out = arr;
+    return FOCK_OK;
+  }
+  const size_t block = (size_t)nper * c.nr;  // elements of one k-point's fields
+  fock_status s = buf.ensure((size_t)c.nsrc * block * sizeof(c128), workspace_cap, "source sub-mesh orbitals");
+  if (s != FOCK_OK) return s;
+  for (int i = 0; i < c.nsrc; ++i) {
+    hipError_t e = hipMemcpyAsync((c128*)buf.ptr + (size_t)i * block, arr + (size_t)c.src[i] * block,
+                                  block * sizeof(c128), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "gather source orbitals");
+  }
+  *out = (const c128*)buf.ptr;
+  return FOCK_OK;
+}
+
+fock_status Plan::apply_op(Cell& c, const c128* u, const c128* phi, int nphi, c128* out, hipStream_t st) {
+  const c128* us = nullptr;
+  fock_status s = sources(c, u, c.nb, srcbuf, st, &us);
+  if (s != FOCK_OK) return s;
+  return general(c, c.fwd(), phi, nphi, us, us, c.nb, out, -1.0 / c.nsrc, false, st);
 }
 
 }  // namespace fockmi
@@ -293,6 +322,16 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
     if (!(d.omega > 0.0) || !std::isfinite(d.omega)) return fail(FOCK_ERR_ARG, "cell %d: omega must be > 0", ci);
     if (!(d.gs > 0.0)) return fail(FOCK_ERR_ARG, "cell %d: gs must be > 0", ci);
     if ((long)d.nk * d.nk > 65535L * 64) return fail(FOCK_ERR_ARG, "cell %d: too many k-points", ci);
+    if (d.nsrc < 0 || d.nsrc > d.nk) return fail(FOCK_ERR_ARG, "cell %d: nsrc = %d outside 0..nk", ci, d.nsrc);
+    if (d.nsrc > 0 && d.src) {
+      std::vector<char> used(d.nk, 0);
+      for (int i = 0; i < d.nsrc; ++i) {
+        const int k = d.src[i];
+        if (k < 0 || k >= d.nk) return fail(FOCK_ERR_ARG, "cell %d: source index %d out of range", ci, k);
+        if (used[k]) return fail(FOCK_ERR_ARG, "cell %d: source index %d repeated", ci, k);
+        used[k] = 1;
+      }
+    }
   }
   Plan* p = new Plan();
   p->prec = prec;
@@ -351,9 +390,7 @@ fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void
   const size_t bp = (size_t)c.nk * nphi * c.nr * sizeof(c128);
   if (overlap(vphi, bp, u_occ, bu) || overlap(vphi, bp, phi, bp))
     return fail(FOCK_ERR_ARG, "vphi overlaps an input array");
-  const double scale = -1.0 / c.nk;
-  return p->general(c, (const c128*)phi, nphi, (const c128*)u_occ, (const c128*)u_occ, c.nb, (c128*)vphi, scale,
-                    false, (hipStream_t)stream);
+  return p->apply_op(c, (const c128*)u_occ, (const c128*)phi, nphi, (c128*)vphi, (hipStream_t)stream);
 }
 
 fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* ex_re, double* ex_im, void* stream) {
@@ -368,9 +405,7 @@ fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* e
   hipStream_t st = (hipStream_t)stream;
   const size_t count = (size_t)c.nk * c.nb * c.nr;
   if ((s = p->vu.ensure(count * sizeof(c128), p->workspace_cap, "energy work array")) != FOCK_OK) return s;
-  if ((s = p->general(c, (const c128*)u_occ, c.nb, (const c128*)u_occ, (const c128*)u_occ, c.nb, (c128*)p->vu.ptr,
-                      -1.0 / c.nk, false, st)) != FOCK_OK)
-    return s;
+  if ((s = p->apply_op(c, (const c128*)u_occ, (const c128*)u_occ, c.nb, (c128*)p->vu.ptr, st)) != FOCK_OK) return s;
   double re = 0, im = 0;
   if ((s = p->dot((const c128*)u_occ, (const c128*)p->vu.ptr, count, st, &re, &im)) != FOCK_OK) return s;
   const double w = (c.gs / 2.0) / c.nk * c.vol / c.nr;
@@ -400,17 +435,38 @@ fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* 
                 (g_u_occ && overlap(g_phi, bp, g_u_occ, bu))))
     return fail(FOCK_ERR_ARG, "g_phi overlaps another array");
   hipStream_t st = (hipStream_t)stream;
-  const double scale = -1.0 / c.nk;
+  const double scale = -1.0 / c.nsrc;
   const c128* U = (const c128*)u_occ;
   const c128* F = (const c128*)phi;
   const c128* G = (const c128*)g_vphi;
+  const c128* Us = nullptr;
+  if ((s = p->sources(c, U, c.nb, p->srcbuf, st, &Us)) != FOCK_OK) return s;
   if (g_phi) {
-    if ((s = p->general(c, G, nphi, U, U, c.nb, (c128*)g_phi, scale, false, st)) != FOCK_OK) return s;
+    if ((s = p->general(c, c.fwd(), G, nphi, Us, Us, c.nb, (c128*)g_phi, scale, false, st)) != FOCK_OK) return s;
   }
   if (g_u_occ) {
-    // targets u (k'), sources (phi or g) at k, kernel K_{k'-k}
-    if ((s = p->general(c, U, c.nb, F, G, nphi, (c128*)g_u_occ, scale, false, st)) != FOCK_OK) return s;
-    if ((s = p->general(c, U, c.nb, G, F, nphi, (c128*)g_u_occ, scale, true, st)) != FOCK_OK) return s;
+    // targets u at the source k-points k', sources (phi or g) at every k, kernel K_{k'-k}
+    c128* gu = (c128*)g_u_occ;
+    hipError_t e;
+    if (c.ds) {
+      const size_t block = (size_t)c.nb * c.nr;
+      if ((s = p->srcout.ensure((size_t)c.nsrc * block * sizeof(c128), p->workspace_cap, "source gradient")) !=
+          FOCK_OK)
+        return s;
+      gu = (c128*)p->srcout.ptr;
+    }
+    if ((s = p->general(c, c.rev(), Us, c.nb, F, G, nphi, gu, scale, false, st)) != FOCK_OK) return s;
+    if ((s = p->general(c, c.rev(), Us, c.nb, G, F, nphi, gu, scale, true, st)) != FOCK_OK) return s;
+    if (c.ds) {
+      // orbitals off the sub-mesh carry no gradient; scatter the sub-mesh rows
+      const size_t block = (size_t)c.nb * c.nr;
+      if ((e = launch_zero((c128*)g_u_occ, (long)c.nk * block, st)) != hipSuccess) return hip_fail(e, "clear gradient");
+      for (int i = 0; i < c.nsrc; ++i) {
+        if ((e = hipMemcpyAsync((c128*)g_u_occ + (size_t)c.src[i] * block, gu + (size_t)i * block,
+                                block * sizeof(c128), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+          return hip_fail(e, "scatter gradient");
+      }
+    }
   }
   return FOCK_OK;
 }

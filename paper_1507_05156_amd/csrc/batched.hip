@@ -106,7 +106,7 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
     B.nthreads = batched_threads(nmax);
     const std::string tkey = [&] {
       std::string k = arch_name() + "/fp32/batched";
-      for (int ci = 0; ci < nc; ++ci) k += "/" + key_for(cells[ci], nphi[ci], "cell");
+      for (int ci = 0; ci < nc; ++ci) k += "/" + key_for(cells[ci], cells[ci].fwd(), nphi[ci], "cell");
       return k;
     }();
     int mult = 1;
@@ -276,13 +276,16 @@ extern "C" fock_status fock_apply_batched(fockmi_plan plan, const void* const* u
       return fail(FOCK_ERR_ARG, "cell %d: vphi overlaps an input array", ci);
   }
   int nmax = 0;
-  for (const Cell& c : p->cells) nmax = std::max(nmax, c.geom.n1);
-  if (p->prec != FOCK_FP32_COMP || nc > kMaxBatchCells || batched_threads(nmax) == 0) {
-    // the plain FP64 path, and plans with a 32^3 cell, run the cells one after another
+  bool any_ds = false;
+  for (const Cell& c : p->cells) {
+    nmax = std::max(nmax, c.geom.n1);
+    any_ds = any_ds || c.ds;
+  }
+  if (p->prec != FOCK_FP32_COMP || nc > kMaxBatchCells || batched_threads(nmax) == 0 || any_ds) {
+    // the plain FP64 path, plans with a 32^3 cell and down-sampled cells run the cells one after another
     for (int ci = 0; ci < nc; ++ci) {
-      Cell& c = p->cells[ci];
-      if ((s = p->general(c, (const c128*)phi[ci], nphi[ci], (const c128*)u_occ[ci], (const c128*)u_occ[ci], c.nb,
-                          (c128*)vphi[ci], -1.0 / c.nk, false, (hipStream_t)stream)) != FOCK_OK)
+      if ((s = p->apply_op(p->cells[ci], (const c128*)u_occ[ci], (const c128*)phi[ci], nphi[ci], (c128*)vphi[ci],
+                           (hipStream_t)stream)) != FOCK_OK)
         return s;
     }
     return FOCK_OK;

@@ -80,5 +80,7 @@ hipError_t launch_to_c64(c64* dst, const c128* src, long count, hipStream_t st);
 hipError_t launch_dot(double* dst, double* partial, int nblk, const c128* a, const c128* b, long count,
                       hipStream_t st);
 hipError_t launch_scale_add(c128* y, const c128* x, double sre, double sim, long count, hipStream_t st);
+// y[i] = 0 for i < count (a kernel, so that it can sit in a captured graph)
+hipError_t launch_zero(c128* y, long count, hipStream_t st);
 
 }  // namespace fockmi

@@ -65,6 +65,11 @@ __global__ void __launch_bounds__(kDotThreads) dot_final_kernel(double* __restri
   }
 }
 
+__global__ void zero_kernel(c128* __restrict__ y, long count) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+    y[i] = c128{0.0, 0.0};
+}
+
 __global__ void scale_add_kernel(c128* __restrict__ y, const c128* __restrict__ x, double sre, double sim,
                                  long count) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
@@ -96,6 +101,11 @@ hipError_t launch_dot(double* dst, double* partial, int nblk, const c128* a, con
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kDotThreads), 0, st, dst, partial, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(c128* y, long count, hipStream_t st) {
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, y, count);
   return hipGetLastError();
 }
 

@@ -97,6 +97,36 @@ fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
   if ((e = hipMemcpy(c.qzero.ptr, qz.data(), qz.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "upload q flags");
 
+  // down-sampling: the source sub-mesh S (validated at plan creation) and the
+  // table rows of (target, source) pairs in both roles
+  c.src.clear();
+  if (d.nsrc > 0 && d.src) {
+    bool identity = d.nsrc == c.nk;
+    for (int i = 0; i < d.nsrc; ++i) {
+      identity = identity && d.src[i] == i;
+      c.src.push_back(d.src[i]);
+    }
+    c.ds = !identity;
+  }
+  if (!c.ds) {
+    c.src.resize(c.nk);
+    for (int k = 0; k < c.nk; ++k) c.src[k] = k;
+  }
+  c.nsrc = (int)c.src.size();
+  if (c.ds) {
+    std::vector<int> ts((size_t)c.nk * c.nsrc), stt((size_t)c.nsrc * c.nk);
+    for (int t = 0; t < c.nk; ++t)
+      for (int i = 0; i < c.nsrc; ++i) ts[(size_t)t * c.nsrc + i] = c.qidx_host[(size_t)t * c.nk + c.src[i]];
+    for (int i = 0; i < c.nsrc; ++i)
+      for (int k = 0; k < c.nk; ++k) stt[(size_t)i * c.nk + k] = c.qidx_host[(size_t)c.src[i] * c.nk + k];
+    if ((s = c.qidx_ts.ensure(ts.size() * sizeof(int), 0, "q index table (sources)")) != FOCK_OK) return s;
+    if ((s = c.qidx_st.ensure(stt.size() * sizeof(int), 0, "q index table (reverse)")) != FOCK_OK) return s;
+    if ((e = hipMemcpy(c.qidx_ts.ptr, ts.data(), ts.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "upload q index");
+    if ((e = hipMemcpy(c.qidx_st.ptr, stt.data(), stt.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "upload q index");
+  }
+
   if ((s = c.kvec.ensure(c.kpts.size() * sizeof(double), 0, "k-points")) != FOCK_OK) return s;
   if ((e = hipMemcpy(c.kvec.ptr, c.kpts.data(), c.kpts.size() * sizeof(double), hipMemcpyHostToDevice)) !=
       hipSuccess)
@@ -156,14 +186,16 @@ void Plan::destroy() {
   prof_events.clear();
   for (Cell& c : cells) {
     c.qidx.release();
+    c.qidx_ts.release();
+    c.qidx_st.release();
     c.qvec.release();
     c.qzero.release();
     c.K64.release();
     c.Kt.release();
     c.kvec.release();
   }
-  for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &psi0, &phiA,
-                    &phiB, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms, &red6, &vloc_buf})
+  for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &srcbuf, &srcout,
+                    &psi0, &phiA, &phiB, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms, &red6, &vloc_buf})
     b->release();
   bstate.release();
   if (host_pinned) (void)hipHostFree(host_pinned);

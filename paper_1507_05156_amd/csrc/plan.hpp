@@ -31,6 +31,14 @@ inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// The k-points a pair sum runs over: targets X at ntk k-points, sources P and
+// M (stored contiguously) at nsk k-points, and qidx[t][s] the kernel-table row
+// of that (target, source) pair.
+struct PairSet {
+  int ntk = 0, nsk = 0;
+  const int* qidx = nullptr;  // device [ntk][nsk]
+};
+
 struct Cell {
   Geom geom{};
   int nr = 0, nk = 0, nb = 0;
@@ -42,6 +50,15 @@ struct Cell {
   DevBuf K64;                 // double[nq][nr], 1/N_r folded, natural slot order
   DevBuf Kt;                  // float[nq][nr], fused-kernel layout (FP32 plans)
   DevBuf kvec;                // double[nk][3] k-points on the device
+  // down-sampling: the source sub-mesh S (all k-points when ds is false)
+  bool ds = false;
+  std::vector<int> src;       // [nsrc] k indices of S
+  int nsrc = 0;
+  DevBuf qidx_ts, qidx_st;    // int[nk][nsrc] (target k, source s), int[nsrc][nk] (source s as target, k)
+  // forward sums: all k-points as targets, S as sources
+  PairSet fwd() const { return {nk, nsrc, (const int*)(ds ? qidx_ts.ptr : qidx.ptr)}; }
+  // the reverse role of the adjoint: S as targets, all k-points as sources
+  PairSet rev() const { return {nsrc, nk, (const int*)(ds ? qidx_st.ptr : qidx.ptr)}; }
 };
 
 // state of the batched persistent launch (fock_apply_batched): buffers whose
@@ -70,7 +87,7 @@ struct Plan {
   size_t workspace_cap = 0;                 // 0 = no cap (FOCKMI_WORKSPACE_CAP overrides)
   size_t batch_cap = size_t(1) << 30;       // plain path: bytes per pair batch
   int xcd_map = 1;
-  DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres;
+  DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres, srcbuf, srcout;
   DevBuf psi0, phiA, phiB, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
@@ -94,12 +111,19 @@ struct Plan {
   fock_status check_ready(int cell) const;
   void destroy();
 
-  fock_status general(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
-                      double scale, bool accumulate, hipStream_t st);
-  fock_status run_plain(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
-                        double scale, bool accumulate, hipStream_t st);
-  fock_status run_fused(Cell& c, const c128* X, int nx, const c128* P, const c128* M, int ns, c128* out,
-                        double scale, bool accumulate, hipStream_t st);
+  // out[t][x] = (accumulate ? out : 0) + scale * sum_{s, b} M[s][b] W(P[s][b], X[t][x]; K_{qidx[t][s]})
+  // over the targets and sources of ps
+  fock_status general(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                      c128* out, double scale, bool accumulate, hipStream_t st);
+  fock_status run_plain(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                        c128* out, double scale, bool accumulate, hipStream_t st);
+  fock_status run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
+                        c128* out, double scale, bool accumulate, hipStream_t st);
+  // the orbitals of the source k-points, contiguous: `arr` itself without
+  // down-sampling, else a copy of its S blocks ([nsrc][nper][nr]) in buf
+  fock_status sources(Cell& c, const c128* arr, int nper, DevBuf& buf, hipStream_t st, const c128** out);
+  // V_x[u] phi into out (forward sums over S, weight 1/|S|)
+  fock_status apply_op(Cell& c, const c128* u, const c128* phi, int nphi, c128* out, hipStream_t st);
   fock_status shadow(DevBuf& buf, const c128* src, size_t count, const char* what, hipStream_t st,
                      const c64** out);
   // sum conj(a) b over count elements in FP64 (fixed order); synchronises st
@@ -114,7 +138,7 @@ struct Plan {
   // batched persistent launch (batched.hip)
   fock_status run_batched(const void* const* u, const void* const* phi, const int* nphi, void* const* vphi,
                           hipStream_t st);
-  std::string key_for(const Cell& c, int nx, const char* what) const;
+  std::string key_for(const Cell& c, const PairSet& ps, int nx, const char* what) const;
   void save_tune();
 };
 

@@ -42,8 +42,9 @@ fock_status Plan::kinetic(Cell& c, const c128* x, int nf, c128* y, const double 
   return FOCK_OK;
 }
 
-// out = (base ? base : 0) + (cre + i cim) * h x, with h = T[a] + v_loc + alpha V_x[u]; out distinct from x
-fock_status Plan::h_apply(Cell& c, const c128* u, const c128* x, c128* out, const c128* base, double cre, double cim,
+// out = (base ? base : 0) + (cre + i cim) * h x, with h = T[a] + v_loc + alpha V_x[u]; out distinct from x.
+// us holds the orbitals of the source k-points (Plan::sources of u).
+fock_status Plan::h_apply(Cell& c, const c128* us, const c128* x, c128* out, const c128* base, double cre, double cim,
                           const double* vloc, const double a[3], double alpha, hipStream_t st) {
   fock_status s;
   if ((s = field_bufs(c, {&kin}, c.nb)) != FOCK_OK) return s;
@@ -51,7 +52,8 @@ fock_status Plan::h_apply(Cell& c, const c128* u, const c128* x, c128* out, cons
   const c128* vx = nullptr;
   if (alpha != 0.0) {
     if ((s = field_bufs(c, {&vxb}, c.nb)) != FOCK_OK) return s;
-    if ((s = general(c, x, c.nb, u, u, c.nb, (c128*)vxb.ptr, -1.0 / c.nk, false, st)) != FOCK_OK) return s;
+    if ((s = general(c, c.fwd(), x, c.nb, us, us, c.nb, (c128*)vxb.ptr, -1.0 / c.nsrc, false, st)) != FOCK_OK)
+      return s;
     vx = (const c128*)vxb.ptr;
   }
   const long count = (long)c.nk * c.nb * c.nr;
@@ -109,9 +111,11 @@ fock_status taylor_step(fockmi_plan plan, int cell, void* psi, const double* vlo
   hipError_t e;
   if ((e = hipMemcpyAsync(psi0, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
   if ((e = hipMemcpyAsync(cur, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
+  const c128* us = nullptr;  // V_x is built from psi(t_n) on the source k-points
+  if ((s = p->sources(c, psi0, c.nb, p->srcbuf, st, &us)) != FOCK_OK) return s;
   for (int m = 1; m <= order; ++m) {
     // phi_m = (-i dt/m) h phi_{m-1}
-    if ((s = p->h_apply(c, psi0, cur, nxt, nullptr, 0.0, -dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+    if ((s = p->h_apply(c, us, cur, nxt, nullptr, 0.0, -dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
     if ((e = launch_scale_add(P, nxt, 1.0, 0.0, count, st)) != hipSuccess) return hip_fail(e, "accumulate step");
     std::swap(cur, nxt);
   }
@@ -138,6 +142,7 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
   fock_status s = common_checks(plan, cell, &p);
   if (s != FOCK_OK) return s;
   Cell& c = p->cells[cell];
+  if (c.ds) return fail(FOCK_ERR_ARG, "taylor_step_vjp is not available for a down-sampled cell");
   if (!psi_n || !g_next || !g_psi || !g_a) return fail(FOCK_ERR_ARG, "NULL pointer");
   if (!aligned16(psi_n) || !aligned16(g_next) || !aligned16(g_psi)) return fail(FOCK_ERR_ARG, "misaligned pointer");
   if ((s = check_step_args(c, dt, order, A_over_c)) != FOCK_OK) return s;
@@ -184,8 +189,8 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
       // cotangent of V_x[u] phi_{m-1} is conj(c_m) alpha lam_m
       if ((e = hipMemsetAsync(gt, 0, bytes, st)) != hipSuccess) return hip_fail(e, "zero");
       if ((e = launch_scale_add(gt, lam, 0.0, alpha * dt / m, count, st)) != hipSuccess) return hip_fail(e, "scale");
-      if ((s = p->general(c, U, c.nb, phim1, gt, c.nb, GP, -1.0 / c.nk, true, st)) != FOCK_OK) return s;
-      if ((s = p->general(c, U, c.nb, gt, phim1, c.nb, GP, -1.0 / c.nk, true, st)) != FOCK_OK) return s;
+      if ((s = p->general(c, c.rev(), U, c.nb, phim1, gt, c.nb, GP, -1.0 / c.nsrc, true, st)) != FOCK_OK) return s;
+      if ((s = p->general(c, c.rev(), U, c.nb, gt, phim1, c.nb, GP, -1.0 / c.nsrc, true, st)) != FOCK_OK) return s;
     }
     // lam_{m-1} = g + conj(c_m) h lam_m
     if ((s = p->h_apply(c, U, lam, lam2, G, 0.0, dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
@@ -211,6 +216,7 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
   fock_status s = common_checks(plan, cell, &p);
   if (s != FOCK_OK) return s;
   Cell& c = p->cells[cell];
+  if (c.ds) return fail(FOCK_ERR_ARG, "taylor_energy is not available for a down-sampled cell");
   if (!psi || !A_over_c || !e_out) return fail(FOCK_ERR_ARG, "NULL pointer");
   if (!aligned16(psi) || (grad_psi && !aligned16(grad_psi))) return fail(FOCK_ERR_ARG, "misaligned pointer");
   const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);

@@ -84,3 +84,17 @@ def test_null_arguments():
     assert lib.fock_plan_create(C.byref(d), 1, N.FOCK_FP64, None, None) == N.FOCK_ERR_ARG
     assert lib.fock_apply(None, 0, None, None, 1, None, None) == N.FOCK_ERR_ARG
     assert lib.fock_plan_destroy(None) == N.FOCK_OK
+
+
+@pytest.mark.parametrize("src,nsrc", [([0, 0], 2), ([0, 5], 2), ([-1], 1), ([0], 3)])
+def test_plan_create_rejects_bad_source_sets(src, nsrc):
+    """Down-sampled source sets: repeated, out-of-range, or more than nk entries."""
+    lib = N.lib()
+    d, keep = _desc()
+    arr = np.ascontiguousarray(np.asarray(src, dtype=np.int32))
+    d.nsrc = nsrc
+    d.src = arr.ctypes.data_as(C.POINTER(C.c_int))
+    h = C.c_void_p()
+    assert lib.fock_plan_create(C.byref(d), 1, N.FOCK_FP64, None, C.byref(h)) == N.FOCK_ERR_ARG
+    assert h.value is None
+    assert b"source" in lib.fock_last_error() or b"nsrc" in lib.fock_last_error()
