@@ -72,6 +72,15 @@ def _fftfreq_int(n: int) -> np.ndarray:
     return np.rint(np.fft.fftfreq(n) * n).astype(np.int64)
 
 
+def submesh(nk1: int, stride: int, nk2: int | None = None, nk3: int | None = None) -> list[int]:
+    """Indices, in gamma_mesh order, of the Gamma-centred sub-mesh keeping every
+    `stride`-th point along each axis (e.g. 4^3 of 12^3 with stride 3)."""
+    nk2 = nk1 if nk2 is None else nk2
+    nk3 = nk1 if nk3 is None else nk3
+    return [(m1 * nk2 + m2) * nk3 + m3 for m1 in range(0, nk1, stride) for m2 in range(0, nk2, stride)
+            for m3 in range(0, nk3, stride)]
+
+
 def orbitals(n, a, kpts, nb, seed, *, orthonormal=True, ecut=ECUT_HA, envelope=ENVELOPE_DIV,
              dtype=np.complex128) -> np.ndarray:
     """Seeded orbitals u[k][b][n1][n2][n3] (periodic parts on the real-space grid)."""
