@@ -198,7 +198,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU decomposition is described in DESIGN.md and not built.", file=sys.stderr)
+              "the multi-GPU decomposition is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
