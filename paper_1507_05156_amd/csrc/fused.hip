@@ -4,8 +4,11 @@
 // (k', j). For each pair it forms rho = conj(P_jk') X (the pair density), does
 // the forward 3D FFT, multiplies by K_{kt-k'} (1/N_r folded into the table),
 // does the inverse FFT and accumulates M_jk' * W. The band sum over j is kept
-// in FP32; after every k' the FP32 partial sum is added to an FP64 running sum
-// with Neumaier compensation, and the final FP64 value is s + c.
+// in FP32 (in registers for N <= 24; for N = 32, whose working field alone
+// fills half the register file, in a per-workgroup global buffer); after every
+// k' the FP32 partial sum is added to an FP64 running sum with Neumaier
+// compensation (the compensation term stored in FP32), and the final FP64
+// value is s + c.
 //
 // Layout on chip, cubic grid of length N, N*N threads:
 //   x phase : thread holds the line along n1 at fixed (m2, m3) -> global loads
