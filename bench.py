@@ -96,8 +96,9 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     the batched persistent launch over three uneven cells (against the same cells
     launched one by one, and against the plain FP64 path for the error), the FP64
     adjoint and Taylor-4 step at 24^3 / 64 k / 16 bands, and E_x (FP32 form) and
-    the FP64 orthonormalisation on the bench workload, and the down-sampled
-    sum as the paper runs it (12^3 k-points, 4^3 source sub-mesh, 16 bands)."""
+    the FP64 orthonormalisation on the bench workload, the down-sampled sum as
+    the paper runs it (12^3 k-points, 4^3 source sub-mesh, 16 bands), and the
+    work of the field against the energy functional at two time steps."""
     out = {}
     # ------------------------------------------- batched persistent launch (three cells)
     cells, us = [], []
@@ -172,6 +173,28 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     del p32, p64, o32, o64, ud
     print(f"[bench] down-sampled 12^3 k / 4^3 q at 16^3: fp32 {pairs_ds / t32:.4e} pairs/s, "
           f"fp64 {pairs_ds / t64:.4e}", file=sys.stderr, flush=True)
+    # ---------------- work of the field vs the energy functional (Eqs. (23)-(24)), two steps
+    from paper_1507_05156_amd import dynamics
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell)
+    u = torch.from_numpy(synth.orbitals(16, cell, kp, 4, seed=synth.seed_for(6, 0))).to(dev)
+    pw = Plan(dict(n=16, a=cell, kpts=kp, nb=4, omega=omega), prec="fp64")
+    runs = {}
+    for dt_w in (0.02, 0.01):
+        nsteps = int(round(0.8 / dt_w))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e_ex, ow, _ = dynamics.work_and_energy(pw, u, 0.5, dt_w, nsteps)
+        torch.cuda.synchronize()
+        runs[dt_w] = (e_ex, ow, (time.perf_counter() - t0) / nsteps)
+    (e1, w1, s1), (e2, w2, s2) = runs[0.02], runs[0.01]
+    out["work_vs_energy_16cube_8k_4b"] = {
+        "pulse": "A0 = 0.5 (A/c), T_d = 0.8 a.u., 1.55 eV, alpha = 1/4, FP64",
+        "dt_0.02": {"E_ex": e1, "Omega_W": w1, "ms_per_step_with_current": s1 * 1e3},
+        "dt_0.01": {"E_ex": e2, "Omega_W": w2, "ms_per_step_with_current": s2 * 1e3},
+        "gap_ratio": abs(w1 - e1) / abs(w2 - e2),
+        "extrapolated_E_ex": 2 * e2 - e1, "extrapolated_Omega_W": 2 * w2 - w1}
+    del pw, u
     # ------------------------------------- E_x and orthonormalisation, the bench workload
     t_e = _timed(lambda: plan32_c2.energy(ud_c2), 1, torch)
     psi = ud_c2.clone()

@@ -345,3 +345,59 @@ def energy_matfree(psi, kpts, a, omega, avec, alpha, vloc=None, gs=2.0):
     grad = 2.0 * w * (tv + alpha * vx)
     grad_a = np.array([w * np.real(np.sum(np.conj(psi) * kinetic_dapply(psi, kpts, a, avec, d))) for d in range(3)])
     return e, grad, grad_a
+
+
+# ------------------------------------------------- current and work (Eqs. (3)-(4), (23)-(24))
+# Velocity gauge, no nonlocal pseudopotential (J_NL = 0), atomic units, electron
+# charge -1. For Bloch orbitals psi = exp(i k.r) u, the cell integral of
+# Re[psi* (-i grad + A/c) psi] is, by Parseval, (Omega/N_r^2) sum_l (k+G_l+A/c) |DFT(u)_l|^2.
+
+def current(psi, kpts, a, avec, gs=2.0):
+    """J(t) = -(1/Omega) (g_s/N_k) sum_{k,b} int_cell Re[psi* (-i grad + A/c) psi] dr."""
+    from .dft import dft3
+    psi = np.asarray(psi, dtype=np.complex128)
+    n = psi.shape[-3:]
+    nr = int(np.prod(n))
+    nk = psi.shape[0]
+    G = gvectors(n, reciprocal(a))
+    total = np.zeros(3)
+    for k in range(nk):
+        p2 = np.sum(np.abs(dft3(psi[k], -1)) ** 2, axis=0)          # sum over bands of |DFT u|^2
+        vel = G + np.asarray(kpts[k]) + np.asarray(avec)            # k + G + A/c
+        total += np.tensordot(p2, vel, axes=([0, 1, 2], [0, 1, 2]))
+    vol = volume(a)
+    return -(1.0 / vol) * (gs / nk) * (vol / nr ** 2) * total
+
+
+def electric_field(t, A0, omega_l, Td, direction=(0.0, 0.0, 1.0)):
+    """E(t) = -(1/c) dA/dt for the pulse of Eq. (21) (pulse_a_over_c), differentiated by hand."""
+    if 0.0 < t < Td:
+        s2 = np.sin(np.pi * t / Td) ** 2
+        ds2 = (np.pi / Td) * np.sin(2.0 * np.pi * t / Td)
+        da = -A0 * (-omega_l * np.sin(omega_l * t) * s2 + np.cos(omega_l * t) * ds2)
+    else:
+        da = 0.0
+    return -da * np.asarray(direction, dtype=np.float64)
+
+
+def work_and_energy(psi0, kpts, a, omega, A0, dt, nsteps, alpha, omega_l, vloc=None, direction=(0, 0, 1),
+                    gs=2.0):
+    """The excitation energy at t_N two ways (the equality of Eq. (23) and Eq. (24) for a
+    functional-derived potential): E_ex = E[psi(t_N); A(t_N)] - E[psi(t_0); A(t_0)] and
+    Omega * W with W = int J.E dt, J(t_n) from psi(t_n), the trapezoid rule over the steps,
+    T_d = nsteps * dt. Returns (E_ex, Omega W, [J(t_n)])."""
+    Td = nsteps * dt
+    psi = np.asarray(psi0, dtype=np.complex128)
+    js, es = [], []
+    for s_ in range(nsteps + 1):
+        t = s_ * dt
+        av = pulse_a_over_c(t, A0, omega_l, Td, direction)
+        js.append(current(psi, kpts, a, av, gs))
+        es.append(electric_field(t, A0, omega_l, Td, direction))
+        if s_ < nsteps:
+            psi = step_matfree(psi, kpts, a, omega, av, dt, alpha, vloc)
+    jE = np.array([np.dot(j, e) for j, e in zip(js, es)])
+    w = dt * (0.5 * jE[0] + jE[1:-1].sum() + 0.5 * jE[-1])
+    e0 = energy_matfree(psi0, kpts, a, omega, pulse_a_over_c(0.0, A0, omega_l, Td, direction), alpha, vloc, gs)[0]
+    eN = energy_matfree(psi, kpts, a, omega, pulse_a_over_c(Td, A0, omega_l, Td, direction), alpha, vloc, gs)[0]
+    return eN - e0, volume(a) * w, np.array(js)

@@ -186,6 +186,18 @@ class Plan:
                                         float(alpha), C.byref(e), _ptr(g), ga if want_grad else None, _stream()))
         return (e.value, g, np.array([ga[0], ga[1], ga[2]])) if want_grad else e.value
 
+    def current(self, psi, a_over_c, cell=0):
+        """J(t) of Eqs. (3)-(4) (velocity gauge, no nonlocal pseudopotential, electron charge -1):
+        -(1/Omega) (g_s/N_k) sum_{k,b} int_cell Re[psi* (-i grad + A/c) psi] dr = -(1/Omega) dE/d(A/c)."""
+        c = self.cells[cell]
+        self._check(psi, cell, c["nb"], "psi")
+        av = (C.c_double * 3)(*[float(x) for x in a_over_c])
+        e = C.c_double()
+        ga = (C.c_double * 3)()
+        # alpha = 0: V_x does not depend on A in the velocity gauge, so only the kinetic term is needed
+        N.check(self._lib.taylor_energy(self._h, cell, _ptr(psi), None, av, 0.0, C.byref(e), None, ga, _stream()))
+        return -np.array([ga[0], ga[1], ga[2]]) / c["vol"]
+
     def orthonormalize(self, psi, cell=0):
         c = self.cells[cell]
         self._check(psi, cell, c["nb"], "psi")

@@ -1,0 +1,68 @@
+"""Pins of the current (Eqs. (3)-(4)) and of the work route to the excitation
+energy (Eq. (24)), which equals the energy-functional route (Eq. (23)) for a
+potential derived from an energy functional, up to an error linear in the time
+step."""
+
+import numpy as np
+
+from oracle import taylor as otaylor
+from oracle.lattice import volume
+from paper_1507_05156_amd import synth
+
+A = 10.26
+OMEGA = 0.106
+OMEGA_L = 0.0569614
+
+
+def small(n=4, nb=2, seed=31):
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(n, cell, kp, nb, seed=seed, ecut=20.0)
+    return cell, kp, u
+
+
+def test_current_is_minus_energy_gradient_over_volume():
+    """J = -(1/Omega) dE/d(A/c): the definition against the FD-pinned gradient of E."""
+    cell, kp, u = small()
+    av = np.array([0.01, -0.03, 0.02])
+    j = otaylor.current(u, kp, cell, av)
+    _, _, ga = otaylor.energy_matfree(u, kp, cell, OMEGA, av, 0.25)
+    assert np.allclose(j, -ga / volume(cell), rtol=1e-12, atol=1e-16)
+
+
+def test_current_of_a_plane_wave():
+    """One plane wave exp(i G.r) per k, normalised: J = -(g_s/(N_k Omega)) sum_k (k + G + A/c)."""
+    cell = np.eye(3) * A
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    n = 4
+    vol = volume(cell)
+    idx = np.indices((n, n, n)).reshape(3, -1).T
+    r = idx / n * A
+    G = 2 * np.pi / A * np.array([1.0, 0.0, -1.0])
+    u = np.exp(1j * r @ G).reshape(1, 1, n, n, n) / np.sqrt(vol)
+    u = np.repeat(u, len(kp), axis=0)
+    av = np.array([0.0, 0.0, 0.05])
+    j = otaylor.current(u, kp, cell, av)
+    ref = -(2.0 / (len(kp) * vol)) * np.sum(kp + G + av, axis=0)
+    assert np.allclose(j, ref, rtol=1e-12)
+
+
+def test_electric_field_is_minus_time_derivative_of_a():
+    Td = 0.6
+    for t in (0.05, 0.2, 0.37, 0.55):
+        h = 1e-6
+        fd = (otaylor.pulse_a_over_c(t + h, 0.05, OMEGA_L, Td) - otaylor.pulse_a_over_c(t - h, 0.05, OMEGA_L, Td)) / (2 * h)
+        assert np.allclose(otaylor.electric_field(t, 0.05, OMEGA_L, Td), -fd, rtol=1e-8, atol=1e-14)
+
+
+def test_work_route_converges_linearly_to_the_energy_route():
+    """|Omega W - E_ex| shrinks about twice when dt halves (HSE functional, alpha = 1/4)."""
+    cell, kp, u = small()
+    T = 1.2
+    diffs = []
+    for nsteps in (20, 40):
+        e_ex, ow, _ = otaylor.work_and_energy(u, kp, cell, OMEGA, 0.5, T / nsteps, nsteps, 0.25, OMEGA_L)
+        diffs.append(abs(ow - e_ex))
+        assert abs(e_ex) > 1e-6
+    ratio = diffs[0] / diffs[1]
+    assert 1.6 < ratio < 2.4, (diffs, ratio)
