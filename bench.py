@@ -179,21 +179,23 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     kp = synth.gamma_mesh(2, cell)
     u = torch.from_numpy(synth.orbitals(16, cell, kp, 4, seed=synth.seed_for(6, 0))).to(dev)
     pw = Plan(dict(n=16, a=cell, kpts=kp, nb=4, omega=omega), prec="fp64")
-    runs = {}
-    for dt_w in (0.02, 0.01):
-        nsteps = int(round(0.8 / dt_w))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e_ex, ow, _ = dynamics.work_and_energy(pw, u, 0.5, dt_w, nsteps)
-        torch.cuda.synchronize()
-        runs[dt_w] = (e_ex, ow, (time.perf_counter() - t0) / nsteps)
-    (e1, w1, s1), (e2, w2, s2) = runs[0.02], runs[0.01]
-    out["work_vs_energy_16cube_8k_4b"] = {
-        "pulse": "A0 = 0.5 (A/c), T_d = 0.8 a.u., 1.55 eV, alpha = 1/4, FP64",
-        "dt_0.02": {"E_ex": e1, "Omega_W": w1, "ms_per_step_with_current": s1 * 1e3},
-        "dt_0.01": {"E_ex": e2, "Omega_W": w2, "ms_per_step_with_current": s2 * 1e3},
-        "gap_ratio": abs(w1 - e1) / abs(w2 - e2),
-        "extrapolated_E_ex": 2 * e2 - e1, "extrapolated_Omega_W": 2 * w2 - w1}
+    leg = {"pulse": "A0 = 0.5 (A/c), T_d = 0.8 a.u., 1.55 eV, alpha = 1/4, FP64"}
+    for pc in (False, True):
+        runs = {}
+        for dt_w in (0.02, 0.01):
+            nsteps = int(round(0.8 / dt_w))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e_ex, ow, _ = dynamics.work_and_energy(pw, u, 0.5, dt_w, nsteps, predictor_corrector=pc)
+            torch.cuda.synchronize()
+            runs[dt_w] = (e_ex, ow, (time.perf_counter() - t0) / nsteps)
+        (e1, w1, s1), (e2, w2, s2) = runs[0.02], runs[0.01]
+        leg["predictor_corrector" if pc else "h_at_t"] = {
+            "dt_0.02": {"E_ex": e1, "Omega_W": w1, "ms_per_step_with_current": s1 * 1e3},
+            "dt_0.01": {"E_ex": e2, "Omega_W": w2, "ms_per_step_with_current": s2 * 1e3},
+            "gap_ratio": abs(w1 - e1) / abs(w2 - e2),
+            "extrapolated_E_ex": 2 * e2 - e1, "extrapolated_Omega_W": 2 * w2 - w1}
+    out["work_vs_energy_16cube_8k_4b"] = leg
     del pw, u
     # ------------------------------------- E_x and orthonormalisation, the bench workload
     t_e = _timed(lambda: plan32_c2.energy(ud_c2), 1, torch)

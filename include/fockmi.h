@@ -124,6 +124,20 @@ fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* 
 fock_status taylor_step(fockmi_plan plan, int cell, void* psi, const double* vloc, const double A_over_c[3],
                         double dt, double alpha, int order, double* max_norm_dev, void* stream);
 
+/* Predictor-corrector Taylor step (Sec. II C, Eqs. (11)-(13)) for the HSE functional:
+ *   psi_pred = T(h(t)) psi          h(t) = T[A_now] + v_loc + alpha V_x[psi(t_n)]
+ *   psi     <- T(h_c) psi           h_c  = T[A_mid] + v_loc + alpha (V_x[psi(t_n)] + V_x[psi_pred]) / 2
+ * with T(h) = sum_{m=0}^{order} (-i dt h)^m / m!, the potentials at t + dt/2
+ * taken as the averages of those at t and at t + dt (built from psi_pred), and
+ * the external field at the midpoint exactly:
+ *   A_now    : host [3] A(t_n)/c;   A_mid : host [3] A(t_n + dt/2)/c
+ * Other arguments and the norm check as taylor_step. Three times the Fock
+ * applications of taylor_step; second order in dt under a time-dependent field,
+ * where taylor_step (A and V_x held at t_n) is first order. No reverse mode. */
+fock_status taylor_step_pc(fockmi_plan plan, int cell, void* psi, const double* vloc, const double A_now[3],
+                           const double A_mid[3], double dt, double alpha, int order, double* max_norm_dev,
+                           void* stream);
+
 /* Reverse mode of taylor_step for the same arguments (psi_n is the state
  * BEFORE the step); not available for a down-sampled cell (FOCK_ERR_ARG).
  * Given g_next, the cotangent of psi(t_n + dt):

@@ -280,6 +280,32 @@ def step_matfree(psi, kpts, a, omega, avec, dt, alpha, vloc=None, order=4, src=N
     return acc
 
 
+def step_pc_matfree(psi, kpts, a, omega, avec_now, avec_mid, dt, alpha, vloc=None, order=4, src=None):
+    """The predictor-corrector step (Sec. II C, Eqs. (11)-(13)) for the HSE functional.
+
+    Predictor: psi_pred = T_order(h(t)) psi with h(t) = T[A(t)/c] + v_loc + alpha V_x[psi].
+    The potentials at t + dt/2 are the averages of those at t and at t + dt built
+    from psi_pred; for HSE that is alpha (V_x[psi] + V_x[psi_pred]) / 2. The
+    field is external and known exactly, so the corrector takes A(t + dt/2).
+    Corrector: psi(t + dt) = T_order(h_c) psi with that averaged operator.
+    """
+    from .fock import fock_apply
+    psi = np.asarray(psi, dtype=np.complex128)
+    pred = step_matfree(psi, kpts, a, omega, avec_now, dt, alpha, vloc, order, src=src)
+    term = psi.copy()
+    acc = psi.copy()
+    for m in range(1, order + 1):
+        y = kinetic_apply(term, kpts, a, avec_mid)
+        if vloc is not None:
+            y = y + np.asarray(vloc).reshape(psi.shape[-3:]) * term
+        if alpha != 0.0:
+            y = y + 0.5 * alpha * (fock_apply(psi, term, kpts, a, omega, src=src)
+                                   + fock_apply(pred, term, kpts, a, omega, src=src))
+        term = (-1j * dt / m) * y
+        acc = acc + term
+    return acc
+
+
 def step_rows(psi, kpts, a, omega, avec, dt, alpha, rows, vloc=None, order=4, src=None):
     """The Taylor step of Eqs. (9)-(10) for the listed orbitals (k, i) only.
 

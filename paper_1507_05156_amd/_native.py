@@ -26,7 +26,7 @@ FOCK_FP64 = 0
 FOCK_FP32_COMP = 1
 
 EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_energy", "fock_vjp", "taylor_step",
-           "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_apply_batched", "fock_profile_enable",
+           "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_apply_batched", "fock_profile_enable",
            "fock_profile_read", "fock_last_error"]
 
 
@@ -61,6 +61,7 @@ def lib():
     L.fock_energy.argtypes = [vp, i, vp, pd, pd, vp]
     L.fock_vjp.argtypes = [vp, i, vp, vp, i, vp, vp, vp, vp]
     L.taylor_step.argtypes = [vp, i, vp, vp, pd, d, d, i, pd, vp]
+    L.taylor_step_pc.argtypes = [vp, i, vp, vp, pd, pd, d, d, i, pd, vp]
     L.taylor_step_vjp.argtypes = [vp, i, vp, vp, pd, d, d, i, vp, vp, pd, vp]
     L.taylor_energy.argtypes = [vp, i, vp, vp, pd, d, pd, vp, pd, vp]
     L.fock_orthonormalize.argtypes = [vp, i, vp, vp]

@@ -159,6 +159,22 @@ class Plan:
         N.check(st)
         return dev.value if want_norm else None
 
+    def taylor_step_pc(self, psi, a_now, a_mid, dt, alpha, vloc=None, order=4, cell=0, want_norm=True):
+        """Predictor-corrector step in place: predictor with A(t_n) and V_x[psi(t_n)], corrector with
+        A(t_n + dt/2) and the average of V_x[psi(t_n)] and V_x[psi_pred]; returns max |norm - 1| (or None)."""
+        c = self.cells[cell]
+        self._check(psi, cell, c["nb"], "psi")
+        an = (C.c_double * 3)(*[float(x) for x in a_now])
+        am = (C.c_double * 3)(*[float(x) for x in a_mid])
+        dev = C.c_double()
+        if vloc is not None:
+            if vloc.dtype != torch.float64 or not vloc.is_cuda or vloc.numel() != c["nr"]:
+                raise ValueError("vloc must be a float64 CUDA tensor with N_r entries")
+        N.check(self._lib.taylor_step_pc(self._h, cell, _ptr(psi), _ptr(vloc) if vloc is not None else None, an, am,
+                                         float(dt), float(alpha), int(order), C.byref(dev) if want_norm else None,
+                                         _stream()))
+        return dev.value if want_norm else None
+
     def taylor_step_vjp(self, psi_n, a_over_c, dt, alpha, g_next, vloc=None, order=4, cell=0):
         """(g_psi_n, g_a) for one Taylor step."""
         c = self.cells[cell]

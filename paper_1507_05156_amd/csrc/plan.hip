@@ -195,7 +195,8 @@ void Plan::destroy() {
     c.kvec.release();
   }
   for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &srcbuf, &srcout,
-                    &psi0, &phiA, &phiB, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms, &red6, &vloc_buf})
+                    &psi0, &phiA, &phiB, &predb, &srcbuf2, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms,
+                    &red6, &vloc_buf})
     b->release();
   bstate.release();
   if (host_pinned) (void)hipHostFree(host_pinned);

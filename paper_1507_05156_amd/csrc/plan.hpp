@@ -88,7 +88,7 @@ struct Plan {
   size_t batch_cap = size_t(1) << 30;       // plain path: bytes per pair batch
   int xcd_map = 1;
   DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres, srcbuf, srcout;
-  DevBuf psi0, phiA, phiB, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
+  DevBuf psi0, phiA, phiB, predb, srcbuf2, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
   bool profiling = false;
@@ -131,8 +131,13 @@ struct Plan {
 
   // propagator pieces (prop_api.hip)
   fock_status kinetic(Cell& c, const c128* x, int nf, c128* y, const double a[3], hipStream_t st);
-  fock_status h_apply(Cell& c, const c128* u, const c128* x, c128* out, const c128* base, double cre, double cim,
-                      const double* vloc, const double a[3], double alpha, hipStream_t st);
+  fock_status h_apply(Cell& c, const c128* us, const c128* us2, const c128* x, c128* out, const c128* base,
+                      double cre, double cim, const double* vloc, const double a[3], double alpha, hipStream_t st);
+  // acc <- x0 + sum_{m=1}^{order} phi_m, phi_m = (-i dt/m) h phi_{m-1}, phi_0 = x0 (acc may alias x0)
+  fock_status taylor_sum(Cell& c, const c128* us, const c128* us2, const c128* x0, c128* acc, const double* vloc,
+                         const double a[3], double dt, double alpha, int order, hipStream_t st);
+  // max over (k, b) of |(Omega/N_r) ||psi_kb||^2 - 1|; synchronises st
+  fock_status norm_dev(Cell& c, const c128* psi, hipStream_t st, double* dev);
   fock_status field_bufs(Cell& c, std::initializer_list<DevBuf*> bufs, int nfields_per_k);
 
   // batched persistent launch (batched.hip)

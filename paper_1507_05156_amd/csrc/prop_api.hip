@@ -43,22 +43,66 @@ fock_status Plan::kinetic(Cell& c, const c128* x, int nf, c128* y, const double 
 }
 
 // out = (base ? base : 0) + (cre + i cim) * h x, with h = T[a] + v_loc + alpha V_x[u]; out distinct from x.
-// us holds the orbitals of the source k-points (Plan::sources of u).
-fock_status Plan::h_apply(Cell& c, const c128* us, const c128* x, c128* out, const c128* base, double cre, double cim,
-                          const double* vloc, const double a[3], double alpha, hipStream_t st) {
+// us holds the orbitals of the source k-points (Plan::sources of u). With a
+// second source set us2, the exchange term is the average alpha (V_x[u] + V_x[u2]) / 2.
+fock_status Plan::h_apply(Cell& c, const c128* us, const c128* us2, const c128* x, c128* out, const c128* base,
+                          double cre, double cim, const double* vloc, const double a[3], double alpha,
+                          hipStream_t st) {
   fock_status s;
   if ((s = field_bufs(c, {&kin}, c.nb)) != FOCK_OK) return s;
   if ((s = kinetic(c, x, c.nb, (c128*)kin.ptr, a, st)) != FOCK_OK) return s;
   const c128* vx = nullptr;
   if (alpha != 0.0) {
     if ((s = field_bufs(c, {&vxb}, c.nb)) != FOCK_OK) return s;
-    if ((s = general(c, c.fwd(), x, c.nb, us, us, c.nb, (c128*)vxb.ptr, -1.0 / c.nsrc, false, st)) != FOCK_OK)
+    const double w = (us2 ? 0.5 : 1.0) / c.nsrc;
+    if ((s = general(c, c.fwd(), x, c.nb, us, us, c.nb, (c128*)vxb.ptr, -w, false, st)) != FOCK_OK) return s;
+    if (us2 && (s = general(c, c.fwd(), x, c.nb, us2, us2, c.nb, (c128*)vxb.ptr, -w, true, st)) != FOCK_OK)
       return s;
     vx = (const c128*)vxb.ptr;
   }
   const long count = (long)c.nk * c.nb * c.nr;
   hipError_t e = launch_hcombine(out, base, (const c128*)kin.ptr, x, vx, vloc, alpha, cre, cim, count, c.nr, st);
   if (e != hipSuccess) return hip_fail(e, "h combine");
+  return FOCK_OK;
+}
+
+fock_status Plan::taylor_sum(Cell& c, const c128* us, const c128* us2, const c128* x0, c128* acc,
+                             const double* vloc, const double a[3], double dt, double alpha, int order,
+                             hipStream_t st) {
+  fock_status s;
+  if ((s = field_bufs(c, {&phiA, &phiB}, c.nb)) != FOCK_OK) return s;
+  const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  const long count = (long)c.nk * c.nb * c.nr;
+  c128* cur = (c128*)phiA.ptr;
+  c128* nxt = (c128*)phiB.ptr;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(cur, x0, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
+  if (acc != x0 && (e = hipMemcpyAsync(acc, x0, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(e, "copy psi");
+  for (int m = 1; m <= order; ++m) {
+    // phi_m = (-i dt/m) h phi_{m-1}
+    if ((s = h_apply(c, us, us2, cur, nxt, nullptr, 0.0, -dt / m, vloc, a, alpha, st)) != FOCK_OK) return s;
+    if ((e = launch_scale_add(acc, nxt, 1.0, 0.0, count, st)) != hipSuccess) return hip_fail(e, "accumulate step");
+    std::swap(cur, nxt);
+  }
+  return FOCK_OK;
+}
+
+fock_status Plan::norm_dev(Cell& c, const c128* psi, hipStream_t st, double* dev) {
+  const int nf = c.nk * c.nb;
+  fock_status s;
+  hipError_t e;
+  if ((s = norms.ensure(nf * sizeof(double), 0, "norms")) != FOCK_OK) return s;
+  if ((e = launch_norms((double*)norms.ptr, psi, nf, c.nr, st)) != hipSuccess) return hip_fail(e, "norms");
+  host_norms.resize(nf);
+  if ((e = hipMemcpyAsync(host_norms.data(), norms.ptr, nf * sizeof(double), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return hip_fail(e, "norm copy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "norm sync");
+  double d = 0.0;
+  const double w = c.vol / c.nr;
+  for (double n2 : host_norms) d = std::max(d, std::fabs(w * n2 - 1.0));
+  *dev = d;
   return FOCK_OK;
 }
 
@@ -101,38 +145,51 @@ fock_status taylor_step(fockmi_plan plan, int cell, void* psi, const double* vlo
   if ((s = check_step_args(c, dt, order, A_over_c)) != FOCK_OK) return s;
   if (!std::isfinite(alpha)) return fail(FOCK_ERR_ARG, "alpha is not finite");
   hipStream_t st = (hipStream_t)stream;
-  if ((s = p->field_bufs(c, {&p->psi0, &p->phiA, &p->phiB}, c.nb)) != FOCK_OK) return s;
+  if ((s = p->field_bufs(c, {&p->psi0}, c.nb)) != FOCK_OK) return s;
   const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
-  const long count = (long)c.nk * c.nb * c.nr;
   c128* P = (c128*)psi;
   c128* psi0 = (c128*)p->psi0.ptr;
-  c128* cur = (c128*)p->phiA.ptr;
-  c128* nxt = (c128*)p->phiB.ptr;
   hipError_t e;
   if ((e = hipMemcpyAsync(psi0, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
-  if ((e = hipMemcpyAsync(cur, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
   const c128* us = nullptr;  // V_x is built from psi(t_n) on the source k-points
   if ((s = p->sources(c, psi0, c.nb, p->srcbuf, st, &us)) != FOCK_OK) return s;
-  for (int m = 1; m <= order; ++m) {
-    // phi_m = (-i dt/m) h phi_{m-1}
-    if ((s = p->h_apply(c, us, cur, nxt, nullptr, 0.0, -dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
-    if ((e = launch_scale_add(P, nxt, 1.0, 0.0, count, st)) != hipSuccess) return hip_fail(e, "accumulate step");
-    std::swap(cur, nxt);
-  }
+  if ((s = p->taylor_sum(c, us, nullptr, psi0, P, vloc, A_over_c, dt, alpha, order, st)) != FOCK_OK) return s;
   if (!max_norm_dev) return FOCK_OK;
-  const int nf = c.nk * c.nb;
-  if ((s = p->norms.ensure(nf * sizeof(double), 0, "norms")) != FOCK_OK) return s;
-  if ((e = launch_norms((double*)p->norms.ptr, P, nf, c.nr, st)) != hipSuccess) return hip_fail(e, "norms");
-  p->host_norms.resize(nf);
-  if ((e = hipMemcpyAsync(p->host_norms.data(), p->norms.ptr, nf * sizeof(double), hipMemcpyDeviceToHost, st)) !=
-      hipSuccess)
-    return hip_fail(e, "norm copy");
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "norm sync");
-  double dev = 0.0;
-  const double w = c.vol / c.nr;
-  for (double n2 : p->host_norms) dev = std::max(dev, std::fabs(w * n2 - 1.0));
-  *max_norm_dev = dev;
-  return dev > 1e-6 ? FOCK_WARN_NORM : FOCK_OK;
+  if ((s = p->norm_dev(c, P, st, max_norm_dev)) != FOCK_OK) return s;
+  return *max_norm_dev > 1e-6 ? FOCK_WARN_NORM : FOCK_OK;
+}
+
+fock_status taylor_step_pc(fockmi_plan plan, int cell, void* psi, const double* vloc, const double A_now[3],
+                           const double A_mid[3], double dt, double alpha, int order, double* max_norm_dev,
+                           void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!psi) return fail(FOCK_ERR_ARG, "psi is NULL");
+  if (!aligned16(psi) || (vloc && ((uintptr_t)vloc & 7u))) return fail(FOCK_ERR_ARG, "misaligned pointer");
+  if ((s = check_step_args(c, dt, order, A_now)) != FOCK_OK) return s;
+  if ((s = check_step_args(c, dt, order, A_mid)) != FOCK_OK) return s;
+  if (!std::isfinite(alpha)) return fail(FOCK_ERR_ARG, "alpha is not finite");
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = p->field_bufs(c, {&p->psi0, &p->predb}, c.nb)) != FOCK_OK) return s;
+  const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  c128* P = (c128*)psi;
+  c128* psi0 = (c128*)p->psi0.ptr;
+  c128* pred = (c128*)p->predb.ptr;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(psi0, P, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy psi");
+  const c128* us = nullptr;
+  if ((s = p->sources(c, psi0, c.nb, p->srcbuf, st, &us)) != FOCK_OK) return s;
+  // predictor with h(t): A(t_n), V_x[psi(t_n)]
+  if ((s = p->taylor_sum(c, us, nullptr, psi0, pred, vloc, A_now, dt, alpha, order, st)) != FOCK_OK) return s;
+  // corrector with A(t_n + dt/2) and the exchange potentials of psi(t_n) and psi_pred averaged
+  const c128* ups = nullptr;
+  if ((s = p->sources(c, pred, c.nb, p->srcbuf2, st, &ups)) != FOCK_OK) return s;
+  if ((s = p->taylor_sum(c, us, ups, psi0, P, vloc, A_mid, dt, alpha, order, st)) != FOCK_OK) return s;
+  if (!max_norm_dev) return FOCK_OK;
+  if ((s = p->norm_dev(c, P, st, max_norm_dev)) != FOCK_OK) return s;
+  return *max_norm_dev > 1e-6 ? FOCK_WARN_NORM : FOCK_OK;
 }
 
 fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const double* vloc,
@@ -160,7 +217,7 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
   hipError_t e;
   if ((e = hipMemcpyAsync(phis, U, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy");
   for (int m = 1; m < order; ++m) {
-    if ((s = p->h_apply(c, U, phis + (size_t)(m - 1) * count, phis + (size_t)m * count, nullptr, 0.0, -dt / m, vloc,
+    if ((s = p->h_apply(c, U, nullptr, phis + (size_t)(m - 1) * count, phis + (size_t)m * count, nullptr, 0.0, -dt / m, vloc,
                         A_over_c, alpha, st)) != FOCK_OK)
       return s;
   }
@@ -193,7 +250,7 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
       if ((s = p->general(c, c.rev(), U, c.nb, gt, phim1, c.nb, GP, -1.0 / c.nsrc, true, st)) != FOCK_OK) return s;
     }
     // lam_{m-1} = g + conj(c_m) h lam_m
-    if ((s = p->h_apply(c, U, lam, lam2, G, 0.0, dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+    if ((s = p->h_apply(c, U, nullptr, lam, lam2, G, 0.0, dt / m, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
     std::swap(lam, lam2);
   }
   if ((e = launch_scale_add(GP, lam, 1.0, 0.0, count, st)) != hipSuccess) return hip_fail(e, "accumulate");
@@ -226,7 +283,7 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
   if ((s = p->field_bufs(c, {&p->lam}, c.nb)) != FOCK_OK) return s;
   c128* hpsi = (c128*)p->lam.ptr;
   const c128* P = (const c128*)psi;
-  if ((s = p->h_apply(c, P, P, hpsi, nullptr, 1.0, 0.0, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+  if ((s = p->h_apply(c, P, nullptr, P, hpsi, nullptr, 1.0, 0.0, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
   double hre, him, xre = 0.0, xim = 0.0;
   if ((s = p->dot(P, hpsi, count, st, &hre, &him)) != FOCK_OK) return s;
   if (alpha != 0.0 && (s = p->dot(P, (const c128*)p->vxb.ptr, count, st, &xre, &xim)) != FOCK_OK) return s;

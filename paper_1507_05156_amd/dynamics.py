@@ -34,8 +34,9 @@ def electric_field(t, A0, omega_l, Td, direction=(0.0, 0.0, 1.0)):
 
 
 def work_and_energy(plan, psi0, A0, dt, nsteps, alpha=0.25, omega_l=0.0569614, vloc=None,
-                    direction=(0.0, 0.0, 1.0), cell=0):
-    """Propagate psi0 through nsteps Taylor steps under the pulse (T_d = nsteps dt) and return
+                    direction=(0.0, 0.0, 1.0), cell=0, predictor_corrector=False):
+    """Propagate psi0 through nsteps Taylor steps under the pulse (T_d = nsteps dt), with
+    h held at t_n or, with predictor_corrector, by the predictor-corrector step, and return
 
     (E_ex, Omega W, J) with E_ex the energy-functional difference between t_N and t_0,
     W = int J.E dt by the trapezoid rule over the time grid, and J [nsteps+1][3] the
@@ -49,7 +50,10 @@ def work_and_energy(plan, psi0, A0, dt, nsteps, alpha=0.25, omega_l=0.0569614, v
         a = pulse_a_over_c(t, A0, omega_l, Td, direction)
         js.append(plan.current(psi, a, cell))
         es.append(electric_field(t, A0, omega_l, Td, direction))
-        if s < nsteps:
+        if s < nsteps and predictor_corrector:
+            a_mid = pulse_a_over_c(t + 0.5 * dt, A0, omega_l, Td, direction)
+            plan.taylor_step_pc(psi, a, a_mid, dt, alpha, vloc=vloc, cell=cell, want_norm=False)
+        elif s < nsteps:
             plan.taylor_step(psi, a, dt, alpha, vloc=vloc, cell=cell, want_norm=False)
     jE = np.array([float(np.dot(j, e)) for j, e in zip(js, es)])
     w = dt * (0.5 * jE[0] + jE[1:-1].sum() + 0.5 * jE[-1])
