@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "FOCK_OK", 1: "FOCK_WARN_NORM", -1: "FOCK_ERR_ARG", -2: "FOCK
 
 FOCK_FP64 = 0
 FOCK_FP32_COMP = 1
+FOCK_FP64_FUSED = 2
 
 EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_energy", "fock_vjp", "taylor_step",
            "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_apply_batched", "fock_profile_enable",

@@ -14,7 +14,7 @@ import torch
 
 from . import _native as N
 
-PRECISIONS = {"fp64": N.FOCK_FP64, "fp32": N.FOCK_FP32_COMP}
+PRECISIONS = {"fp64": N.FOCK_FP64, "fp32": N.FOCK_FP32_COMP, "fp64f": N.FOCK_FP64_FUSED}
 
 
 def _ptr(t):
@@ -31,8 +31,9 @@ class Plan:
     cells : list of dicts with keys n (int or 3-tuple), a (3x3 rows), kpts ([nk][3]),
             nb, omega, gs (default 2.0), and optionally src: the k indices of a
             down-sampled source sub-mesh (the pair sum runs over them with weight 1/len(src))
-    prec  : "fp64" (plain staged FP64 path) or "fp32" (fused complex64 pair FFTs with
-            compensated FP64 accumulation)
+    prec  : "fp64" (plain staged FP64 path), "fp32" (fused complex64 pair FFTs with
+            compensated FP64 accumulation) or "fp64f" (fused kernel in FP64 throughout for
+            cubic grids of length 16, 20, 24; other cells take the plain path)
     """
 
     def __init__(self, cells, prec="fp64", tune_cache=None):

@@ -256,7 +256,7 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
 std::string Plan::key_for(const Cell& c, const PairSet& ps, int nx, const char* what) const {
   char buf[192];
   std::snprintf(buf, sizeof(buf), "%s/%s/%s/n%dx%dx%d/nt%d/ns%d/nb%d/nx%d", arch_name().c_str(),
-                prec == FOCK_FP32_COMP ? "fp32" : "fp64", what, c.geom.n1, c.geom.n2, c.geom.n3, ps.ntk, ps.nsk, c.nb,
+                prec == FOCK_FP32_COMP ? "fp32" : (c.f64f ? "fp64f" : "fp64"), what, c.geom.n1, c.geom.n2, c.geom.n3, ps.ntk, ps.nsk, c.nb,
                 nx);
   return buf;
 }
@@ -268,7 +268,37 @@ void Plan::save_tune() {
 fock_status Plan::general(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
                           c128* out, double scale, bool accumulate, hipStream_t st) {
   if (prec == FOCK_FP32_COMP) return run_fused(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
+  if (c.f64f) return run_fused64(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
   return run_plain(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
+}
+
+fock_status Plan::run_fused64(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M,
+                              int ns, c128* out, double scale, bool accumulate, hipStream_t st) {
+  const int nitems = ps.ntk * nx;
+  fock_status s;
+  const size_t acc_elems = fused64_acc_scratch_elems(c.geom.n1, nitems);
+  if (acc_elems && (s = accs.ensure(acc_elems * sizeof(c128), workspace_cap, "FP64 sums")) != FOCK_OK) return s;
+  Fused64Args a{};
+  a.X = X;
+  a.P = P;
+  a.M = M;
+  a.Kt = (const double*)c.Kt64.ptr;
+  a.qidx = ps.qidx;
+  a.out = out;
+  a.accs = (c128*)accs.ptr;
+  a.nk = ps.nsk;
+  a.nx = nx;
+  a.nb = ns;
+  a.item0 = 0;
+  a.nitems = nitems;
+  a.scale = scale;
+  a.accumulate = accumulate ? 1 : 0;
+  a.xcd_map = xcd_map;
+  hipError_t e;
+  if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
+  if ((e = launch_fused64_apply(c.geom.n1, a, st)) != hipSuccess) return hip_fail(e, "fused FP64 pair kernel");
+  if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
+  return FOCK_OK;
 }
 
 fock_status Plan::sources(Cell& c, const c128* arr, int nper, DevBuf& buf, hipStream_t st, const c128** out) {
@@ -308,7 +338,8 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
   if (!out) return fail(FOCK_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!cells || ncells < 1) return fail(FOCK_ERR_ARG, "need at least one cell");
-  if (prec != FOCK_FP64 && prec != FOCK_FP32_COMP) return fail(FOCK_ERR_ARG, "unknown precision %d", (int)prec);
+  if (prec != FOCK_FP64 && prec != FOCK_FP32_COMP && prec != FOCK_FP64_FUSED)
+    return fail(FOCK_ERR_ARG, "unknown precision %d", (int)prec);
   for (int ci = 0; ci < ncells; ++ci) {
     const fock_cell_desc& d = cells[ci];
     for (int dd = 0; dd < 3; ++dd)

@@ -20,7 +20,7 @@
 // the transposes between phases. When a full complex64 field does not fit in
 // LDS (N = 32), each transpose runs in two rounds over half of the field, with
 // the thread map arranged so that a thread never holds two lines at once.
-#include "kernels.hpp"
+#include "fused_common.hpp"
 
 namespace fockmi {
 
@@ -66,22 +66,6 @@ constexpr int fused_lds_elems() {
 
 namespace {
 
-// LDS element at a per-thread byte offset plus a compile-time byte offset; the
-// constant folds into the instruction's 16-bit immediate when below 64 KiB.
-template <unsigned C>
-__device__ __forceinline__ c64& lds_at(c64* lds, unsigned off) {
-  static_assert(C < 65536u, "LDS immediate offset out of range");
-  return *reinterpret_cast<c64*>(reinterpret_cast<char*>(lds) + off + C);
-}
-
-// Hides a value from loop-invariant code motion: addresses derived from it are
-// formed where they are used (base register + immediate) instead of being
-// hoisted out of the pair loop, one register each, and spilled.
-__device__ __forceinline__ unsigned opaque(unsigned x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   const double t = s + x;
   if (fabs(s) >= fabs(x)) c += (s - t) + x;
@@ -107,8 +91,10 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   constexpr int NBK = N / NPH;     // l1 values per round of the y<->z transpose
   constexpr bool ACCREG = fused_acc_in_regs<N>();
   item = __builtin_amdgcn_readfirstlane(item);
-  // round indices are wave-uniform (rounds are whole waves); readfirstlane
-  // lets the compiler branch on them instead of masking lanes
+  // round indices are wave-uniform (rounds are whole waves: 512 and 256 threads
+  // at N = 32, a single round below); readfirstlane lets the compiler branch on
+  // them instead of masking lanes
+  static_assert(NPH == 1 || (TPG % 64 == 0 && (NBK * H) % 64 == 0), "rounds must be whole waves");
   const int grp = __builtin_amdgcn_readfirstlane(t / TPG);
   const int tl = t % TPG;
   const int hl = tl % H;

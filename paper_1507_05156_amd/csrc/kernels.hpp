@@ -58,6 +58,28 @@ hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int var
 int fused_variants(int n);
 size_t fused_acc_scratch_elems(int n, int nslots);  // c64 elements needed in accs (0 if registers)
 
+// ---- fused FP64 form -------------------------------------------------------
+struct Fused64Args {
+  const c128* X;      // [ntk][nx][nr] targets
+  const c128* P;      // [nk][nb][nr] conjugated in the pair density (sources)
+  const c128* M;      // [nk][nb][nr] multiplier (sources)
+  const double* Kt;   // [nq][nr] fused layout (FP64 transposes), 1/N_r folded
+  const int* qidx;    // [ntk][nk] table row of (target k, source k')
+  c128* out;          // [ntk][nx][nr] result
+  c128* accs;         // per-workgroup FP64 sums when they do not fit in registers
+  int nk, nx, nb;     // sources, targets per k, bands per source
+  int item0, nitems;  // work items [item0, item0 + nitems) of ntk*nx
+  double scale;       // e.g. -1/|S|
+  int accumulate;     // 1: add to the existing out
+  int xcd_map;
+};
+bool fused64_supported(int n);                        // cubic grid lengths with a fused FP64 kernel
+int fused64_phases(int n);                            // rounds of the x<->y transpose (table layout)
+size_t fused64_acc_scratch_elems(int n, int nslots);  // c128 elements needed in accs (0 if registers)
+hipError_t launch_fused64_apply(int n, const Fused64Args& a, hipStream_t st);
+// FP64 copy of the tables in the fused FP64 kernel's layout (nph rounds)
+hipError_t launch_build_table_fused64(double* Kt, const double* K, int nq, int n, int nph, hipStream_t st);
+
 // Persistent launch over several cells: nwg workgroups of nthreads pop entries
 // (queue[3i] = cell, queue[3i+1] = target item, queue[3i+2] = a second target
 // of the same 16^3 cell or -1) from kBatchQueues sub-queues; sub-queue x holds

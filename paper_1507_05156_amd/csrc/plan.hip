@@ -141,6 +141,14 @@ fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
         hipSuccess)
       return hip_fail(e, "FP32 kernel table");
   }
+  if (prec == FOCK_FP64_FUSED && c.geom.n1 == c.geom.n2 && c.geom.n2 == c.geom.n3 && fused64_supported(c.geom.n1)) {
+    if ((s = c.Kt64.ensure((size_t)c.nq * c.nr * sizeof(double), 0, "fused FP64 kernel tables")) != FOCK_OK)
+      return s;
+    if ((e = launch_build_table_fused64((double*)c.Kt64.ptr, (const double*)c.K64.ptr, c.nq, c.geom.n1,
+                                        fused64_phases(c.geom.n1), 0)) != hipSuccess)
+      return hip_fail(e, "fused FP64 kernel table");
+    c.f64f = true;
+  }
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "plan set-up");
   return FOCK_OK;
 }
@@ -192,6 +200,7 @@ void Plan::destroy() {
     c.qzero.release();
     c.K64.release();
     c.Kt.release();
+    c.Kt64.release();
     c.kvec.release();
   }
   for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &srcbuf, &srcout,

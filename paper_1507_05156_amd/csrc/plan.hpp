@@ -49,6 +49,8 @@ struct Cell {
   DevBuf qidx, qvec, qzero;   // int[nk*nk], double[nq*3], int[nq]
   DevBuf K64;                 // double[nq][nr], 1/N_r folded, natural slot order
   DevBuf Kt;                  // float[nq][nr], fused-kernel layout (FP32 plans)
+  DevBuf Kt64;                // double[nq][nr], fused FP64 kernel layout (FP64-fused plans)
+  bool f64f = false;          // this cell runs the fused FP64 kernel
   DevBuf kvec;                // double[nk][3] k-points on the device
   // down-sampling: the source sub-mesh S (all k-points when ds is false)
   bool ds = false;
@@ -119,6 +121,8 @@ struct Plan {
                         c128* out, double scale, bool accumulate, hipStream_t st);
   fock_status run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
                         c128* out, double scale, bool accumulate, hipStream_t st);
+  fock_status run_fused64(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M,
+                          int ns, c128* out, double scale, bool accumulate, hipStream_t st);
   // the orbitals of the source k-points, contiguous: `arr` itself without
   // down-sampling, else a copy of its S blocks ([nsrc][nper][nr]) in buf
   fock_status sources(Cell& c, const c128* arr, int nper, DevBuf& buf, hipStream_t st, const c128** out);

@@ -58,7 +58,8 @@ __global__ void build_table_f64_kernel(double* __restrict__ K, const double* __r
 
 // Fused layout: value index l3 of thread t in the z phase of the fused kernel,
 // with the same (l1, l2) <- t map as that kernel (see fused.hip).
-__global__ void build_table_fused_kernel(float* __restrict__ Kt, const double* __restrict__ K, int nq, int n,
+template <typename T>
+__global__ void build_table_fused_kernel(T* __restrict__ Kt, const double* __restrict__ K, int nq, int n,
                                          int nph) {
   const int nt = n * n;
   const long nr = (long)nt * n;
@@ -71,7 +72,7 @@ __global__ void build_table_fused_kernel(float* __restrict__ Kt, const double* _
   const int grp = t / tpg, tl = t % tpg;
   const int l2 = tl % h + h * grp;
   const int l1 = tl / h;
-  Kt[(long)q * nr + idx] = (float)K[(long)q * nr + ((long)l1 * n + l2) * n + l3];
+  Kt[(long)q * nr + idx] = (T)K[(long)q * nr + ((long)l1 * n + l2) * n + l3];
 }
 
 }  // namespace
@@ -97,8 +98,21 @@ hipError_t launch_build_table_fused(float* Kt, const double* K, int nq, int n, h
   for (int q0 = 0; q0 < nq; q0 += 65535) {
     const int cnt = nq - q0 < 65535 ? nq - q0 : 65535;
     dim3 grid((unsigned)((nr + 255) / 256), (unsigned)cnt);
-    hipLaunchKernelGGL(build_table_fused_kernel, grid, dim3(256), 0, st, Kt + (long)q0 * nr, K + (long)q0 * nr,
-                       cnt, n, fused_phases(n));
+    hipLaunchKernelGGL(build_table_fused_kernel<float>, grid, dim3(256), 0, st, Kt + (long)q0 * nr,
+                       K + (long)q0 * nr, cnt, n, fused_phases(n));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_build_table_fused64(double* Kt, const double* K, int nq, int n, int nph, hipStream_t st) {
+  const long nr = (long)n * n * n;
+  for (int q0 = 0; q0 < nq; q0 += 65535) {
+    const int cnt = nq - q0 < 65535 ? nq - q0 : 65535;
+    dim3 grid((unsigned)((nr + 255) / 256), (unsigned)cnt);
+    hipLaunchKernelGGL(build_table_fused_kernel<double>, grid, dim3(256), 0, st, Kt + (long)q0 * nr,
+                       K + (long)q0 * nr, cnt, n, nph);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
