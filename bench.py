@@ -140,13 +140,30 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     psi = u3.clone()
     t_step = _timed(lambda: plan.taylor_step(psi, [0.0, 0.0, 0.01], 0.02, 0.25), 1, torch)
     t_apply = _timed(lambda: plan.apply(u3), 1, torch)
+    ref = plan.apply(u3)
     out["fp64_24cube_64k_16b"] = {
         "pairs_per_apply": p3, "apply_ms": t_apply * 1e3, "apply_pairs_per_s": p3 / t_apply,
         "vjp_ms": t_vjp * 1e3, "vjp_pair_ffts_per_s": 3 * p3 / t_vjp,
         "taylor4_step_ms": t_step * 1e3, "taylor4_pair_ffts_per_s": 4 * p3 / t_step}
-    del plan, u3, g, psi
     print(f"[bench] fp64 24^3: apply {t_apply * 1e3:.0f} ms, vjp {t_vjp * 1e3:.0f} ms, "
           f"taylor step {t_step * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    del plan, psi
+    # the same calls through the fused FP64 form
+    planf = Plan(dict(n=u.shape[2], a=a, kpts=kp, nb=nb, omega=omega), prec="fp64f")
+    got = planf.apply(u3)
+    rel = ((got - ref).reshape(nk, -1).norm(dim=1) / ref.reshape(nk, -1).norm(dim=1)).max().item()
+    planf.vjp(u3, u3, g)
+    t_vjpf = _timed(lambda: planf.vjp(u3, u3, g), 1, torch)
+    psi = u3.clone()
+    t_stepf = _timed(lambda: planf.taylor_step(psi, [0.0, 0.0, 0.01], 0.02, 0.25), 1, torch)
+    t_applyf = _timed(lambda: planf.apply(u3, out=got), 3, torch)
+    out["fp64_fused_24cube_64k_16b"] = {
+        "apply_ms": t_applyf * 1e3, "apply_pairs_per_s": p3 / t_applyf, "speedup_vs_plain": t_apply / t_applyf,
+        "max_rel_err_per_k_vs_plain": rel,
+        "vjp_ms": t_vjpf * 1e3, "taylor4_step_ms": t_stepf * 1e3}
+    print(f"[bench] fp64 fused 24^3: apply {t_applyf * 1e3:.0f} ms ({t_apply / t_applyf:.2f}x plain), "
+          f"vjp {t_vjpf * 1e3:.0f} ms, taylor step {t_stepf * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    del planf, u3, g, psi, got, ref
     # ------------------- down-sampling as the paper runs it: 12^3 k-mesh, 4^3 source sub-mesh
     cell = synth.cubic_cell()
     kp = synth.gamma_mesh(12, cell)
@@ -164,15 +181,23 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     t64 = _timed(lambda: p64.apply(ud, out=o64), 1, torch)
     nk = len(kp)
     rel = ((o32 - o64).reshape(nk, -1).norm(dim=1) / o64.reshape(nk, -1).norm(dim=1)).max().item()
+    del p64
+    p64f = Plan(desc, prec="fp64f")
+    o64f = p64f.apply(ud)
+    t64f = _timed(lambda: p64f.apply(ud, out=o64f), 3, torch)
+    rel64f = ((o64f - o64).reshape(nk, -1).norm(dim=1) / o64.reshape(nk, -1).norm(dim=1)).max().item()
+    del p64f, o64f
     out["downsampled_12cube_k_4cube_q"] = {
         "grid": "16^3", "k_points": nk, "source_k_points": len(src), "bands": 16, "pairs": pairs_ds,
         "fp32_pairs_per_s": pairs_ds / t32, "fp32_ms": t32 * 1e3,
         "fp64_plain_pairs_per_s": pairs_ds / t64, "fp64_plain_ms": t64 * 1e3,
+        "fp64_fused_pairs_per_s": pairs_ds / t64f, "fp64_fused_ms": t64f * 1e3,
+        "fp64_fused_max_rel_err_per_k_vs_plain": rel64f,
         "fp32_max_rel_err_per_k_vs_fp64": rel,
         "pairs_without_downsampling": (nk * 16) ** 2}
-    del p32, p64, o32, o64, ud
+    del p32, o32, o64, ud
     print(f"[bench] down-sampled 12^3 k / 4^3 q at 16^3: fp32 {pairs_ds / t32:.4e} pairs/s, "
-          f"fp64 {pairs_ds / t64:.4e}", file=sys.stderr, flush=True)
+          f"fp64 plain {pairs_ds / t64:.4e}, fp64 fused {pairs_ds / t64f:.4e}", file=sys.stderr, flush=True)
     # ---------------- work of the field vs the energy functional (Eqs. (23)-(24)), two steps
     from paper_1507_05156_amd import dynamics
     cell = synth.cubic_cell()
