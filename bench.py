@@ -368,7 +368,7 @@ def main():
                    "pairs_per_step": pairs, "ffts_per_step": 2 * pairs, "kernel": "fused FP32 pair kernel"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"fused_apply_kernel<{n}>", "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,
+                     "kernel": f"fused_lockstep_kernel<{n}>" if n == 32 else f"fused_apply_kernel<{n}>", "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,
                      "alg_bytes_per_pair": nr * 8, "alg_bytes_per_launch": alg_bytes, "pairs_per_launch": pairs,
                      "traffic_bytes_per_pair": traffic / pairs if traffic else None,
                      "traffic_GBs": traffic / kern_avg_s / 1e9 if traffic else None,

@@ -185,9 +185,17 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   const int nitems = ps.ntk * nx;
   if ((s = comp.ensure((size_t)nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
     return s;
-  const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, nitems);
+  // the lockstep form runs one workgroup per CU (a multiple of 8: one share per XCD)
+  LockstepCfg ls{nullptr, (num_cus / 8) * 8};
+  const bool has_ls = fused_has_lockstep(c.geom.n1) && ls.nwg >= 8;
+  if (has_ls) {
+    if ((s = sync.ensure(kLockstepInts * sizeof(int), workspace_cap, "lockstep counters")) != FOCK_OK) return s;
+    ls.counters = (int*)sync.ptr;
+  }
+  const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, std::max(nitems, ls.nwg));
   if (acc_elems && (s = accs.ensure(acc_elems * sizeof(c64), workspace_cap, "FP32 partial sums")) != FOCK_OK)
     return s;
+  const int nvar = fused_variants(c.geom.n1) - (fused_has_lockstep(c.geom.n1) && !has_ls ? 1 : 0);
   FusedArgs a{};
   a.X = Xs;
   a.P = Ps;
@@ -206,14 +214,14 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   a.accumulate = accumulate ? 1 : 0;
   a.xcd_map = xcd_map;
   a.n = c.geom.n1;
-  int variant = 0;
+  int variant = (c.geom.n1 == 32 && has_ls) ? fused32_variant : 0;
   hipError_t e;
   const std::string key = key_for(c, ps, nx, "fused");
   TuneEntry te;
   if (tune.get(key, &te)) {
     variant = (int)te.fields["variant"];
     a.xcd_map = (int)te.fields["xcd_map"];
-    if (variant >= fused_variants(c.geom.n1)) variant = 0;
+    if (variant >= nvar) variant = 0;
   } else if (tuning && !accumulate) {
     // measure every candidate on this call's data (each writes the same result)
     hipEvent_t e0, e1;
@@ -221,11 +229,11 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
     double best = 1e300;
     int bv = 0, bx = 1;
-    for (int v = 0; v < fused_variants(c.geom.n1); ++v) {
+    for (int v = 0; v < nvar; ++v) {
       for (int x = 0; x < 2; ++x) {
         a.xcd_map = x;
         (void)hipEventRecord(e0, st);
-        if ((e = launch_fused_apply(c.geom.n1, a, st, v)) != hipSuccess) return hip_fail(e, "fused pair kernel");
+        if ((e = launch_fused_apply(c.geom.n1, a, st, v, &ls)) != hipSuccess) return hip_fail(e, "fused pair kernel");
         (void)hipEventRecord(e1, st);
         if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
         float ms = 0.f;
@@ -248,7 +256,8 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     a.xcd_map = bx;
   }
   if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
-  if ((e = launch_fused_apply(c.geom.n1, a, st, variant)) != hipSuccess) return hip_fail(e, "fused pair kernel");
+  if ((e = launch_fused_apply(c.geom.n1, a, st, variant, &ls)) != hipSuccess)
+    return hip_fail(e, "fused pair kernel");
   if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
   return FOCK_OK;
 }

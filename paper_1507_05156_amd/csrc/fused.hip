@@ -10,6 +10,10 @@
 // compensation (the compensation term stored in FP32), and the final FP64
 // value is s + c.
 //
+// At N = 32 a persistent form runs one workgroup per CU and keeps the
+// workgroups of each XCD in step pair by pair (fused_lockstep_kernel), so that
+// the sources they all read in the same order come from L2.
+//
 // Layout on chip, cubic grid of length N, N*N threads:
 //   x phase : thread holds the line along n1 at fixed (m2, m3) -> global loads
 //             and stores of neighbouring lanes hit neighbouring addresses;
@@ -48,13 +52,20 @@ constexpr bool fused_acc_in_regs() {
 // whole group is in flight, so a pair costs a few memory round trips instead
 // of one per line element. Group sizes per grid length: pair-product operands,
 // kernel values, multipliers (0: element by element, where the registers are
-// full, as for N = 32 whose multiplier loads would spill).
+// full, as for N = 32 whose multiplier loads would spill). At N = 32 the
+// pair-product operands go in two groups of 16: one group of 32 (128 VGPRs of
+// load results) pushed the allocator into spills that cost more than the
+// second round trip.
 template <int N>
-constexpr int grp_px() { return N == 16 ? 8 : (N <= 24 ? 4 : N); }
+constexpr int grp_px() { return N == 16 ? 8 : (N <= 24 ? 4 : 16); }
 template <int N>
 constexpr int grp_k() { return N <= 24 ? N : 8; }
 template <int N>
 constexpr int grp_m() { return N == 16 ? 8 : (N <= 24 ? 4 : 0); }
+// Elements whose loads run ahead of their use in the FP64 flush (0: element by
+// element, with the loads skipped where the flags make them unused).
+template <int N>
+constexpr int flush_depth() { return N == 32 ? 4 : 0; }
 
 template <int N>
 constexpr int fused_lds_elems() {
@@ -66,12 +77,60 @@ constexpr int fused_lds_elems() {
 
 namespace {
 
+// s + c += x, with the rounding error of each addition carried in c. The
+// error terms are exact only if every operation rounds on its own: no
+// contraction into FMAs here or where x is formed.
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+#pragma clang fp contract(off)
   const double t = s + x;
   if (fabs(s) >= fabs(x)) c += (s - t) + x;
   else c += (x - t) + s;
   s = t;
 }
+
+// Pair hooks: called by every thread at the start of each pair p = k' * nb + j
+// of a work item, before the pair's loads.
+struct NoPairHook {
+  __device__ __forceinline__ void operator()(int) {}
+};
+
+// Soft lockstep of the workgroups of one XCD (persistent launch). Before each
+// pair a workgroup counts itself in on its XCD's counter and waits until every
+// workgroup of the XCD that has an item in this round has arrived at the same
+// pair. All of them read the sources in the same (k', j) order, so the source
+// orbitals (and, for targets of one k, the kernel values) then come from L2
+// once per XCD instead of once per workgroup. The wait is bounded: after
+// kLockstepPolls polls thread 0 stops taking part, and its peers stop at their
+// next wait, so the result never depends on the counter, only the speed does.
+// The state lives in LDS (thread 0 alone touches it), so it holds no registers
+// across the pair.
+constexpr int kLockstepPolls = 4096;
+struct LockstepState {
+  int* cnt;     // this XCD's arrival counter (zero at launch)
+  int target;   // arrivals of the XCD's workgroups up to and including this pair
+  int part;     // workgroups of the XCD with an item in this round
+  int live;     // 0 once a wait has timed out
+};
+struct XcdLockstep {
+  LockstepState* st;  // in LDS
+  __device__ __forceinline__ void operator()(int) {
+    if (threadIdx.x == 0 && st->live) {
+      int* cnt = st->cnt;
+      __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int target = st->target + st->part;
+      st->target = target;
+      int n = 0;
+      while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++n > kLockstepPolls) {
+          st->live = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+  }
+};
 
 // One work item (target field X[kt][s]) of the fused pair computation, run by
 // the N*N threads t = 0 .. N*N-1 of one thread group, with `lds` its own LDS
@@ -80,9 +139,9 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 // wave on the same straight-line code); their FP64 stores are steered past the
 // end of the buffer, where raw buffer stores are dropped. `item` must be
 // uniform over each wave.
-template <int N>
+template <int N, class Hook>
 __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc_slot, c64* __restrict__ lds,
-                                           int t, bool twin) {
+                                           int t, bool twin, Hook& hook) {
   constexpr int NTI = N * N;
   constexpr int NR = N * N * N;
   constexpr int NPH = fused_nph<N>();
@@ -143,6 +202,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
     const bool first_ks = (ks == 0);
     const bool last_ks = (ks == a.nk - 1);
     for (int j = 0; j < a.nb; ++j) {
+      hook(ks * a.nb + j);
       const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
       const rsrc_t rM = make_rsrc(a.M + ((long)ks * a.nb + j) * NR, FB64);
       c64 v[N];
@@ -252,7 +312,10 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
         });
       } else {
         // the position of j in the band loop is uniform: one branch per pair
-        // selects the accumulator traffic, none per element
+        // selects the accumulator traffic, none per element. The loads go
+        // element by element: with the line in registers, loading ahead (in
+        // groups, or a few elements in flight) made the allocator spill more
+        // than the overlap gained.
         auto mac = [&](auto load_acc, auto store_acc) {
 #pragma unroll
           for (int m1 = 0; m1 < N; ++m1) {
@@ -274,32 +337,68 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
         }
       }
       if (last_j) {
+#pragma clang fp contract(off)
         // fold the FP32 band sum of this k' into the FP64 running sum
+        if constexpr (flush_depth<N>() == 0) {
 #pragma unroll
-        for (int m1 = 0; m1 < N; ++m1) {
-          const unsigned so = (unsigned)(m1 * NTI * 16);
-          const double xr = a.scale * (double)v[m1].re;
-          const double xi = a.scale * (double)v[m1].im;
-          double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-          if (!first_ks || a.accumulate) {
-            const c128 o = ld_c128(rOut, voff_f, so);
-            sr = o.re;
-            si = o.im;
+          for (int m1 = 0; m1 < N; ++m1) {
+            const unsigned so = (unsigned)(m1 * NTI * 16);
+            const double xr = a.scale * (double)v[m1].re;
+            const double xi = a.scale * (double)v[m1].im;
+            double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
+            if (!first_ks || a.accumulate) {
+              const c128 o = ld_c128(rOut, voff_f, so);
+              sr = o.re;
+              si = o.im;
+            }
+            if (!first_ks) {
+              const c64 c = ld_c64(rComp, voff_c, so / 2);
+              cr = c.re;
+              ci = c.im;
+            }
+            neumaier(sr, cr, xr);
+            neumaier(si, ci, xi);
+            if (last_ks) {
+              st_c128(c128{sr + cr, si + ci}, rOut, voff_f, so);
+            } else {
+              st_c128(c128{sr, si}, rOut, voff_f, so);
+              // the compensation is a rounding-error term (~1e-16 |s|): FP32 keeps it
+              st_c64(c64{(float)cr, (float)ci}, rComp, voff_c, so / 2);
+            }
           }
-          if (!first_ks) {
-            const c64 c = ld_c64(rComp, voff_c, so / 2);
-            cr = c.re;
-            ci = c.im;
-          }
-          neumaier(sr, cr, xr);
-          neumaier(si, ci, xi);
-          if (last_ks) {
-            st_c128(c128{sr + cr, si + ci}, rOut, voff_f, so);
-          } else {
-            st_c128(c128{sr, si}, rOut, voff_f, so);
-            // the compensation is a rounding-error term (~1e-16 |s|): FP32 keeps it
+        } else {
+          // every element is loaded and stored unconditionally (the buffers are
+          // whole fields) and the uniform flags only select values, so the loop
+          // is straight-line code whose loads run ahead of their use
+          const bool use_out = !first_ks || a.accumulate;
+          const bool use_comp = !first_ks;
+          constexpr int D = flush_depth<N>();
+          c128 oq[D];
+          c64 cq[D];
+          auto issue = [&](auto m) {
+            constexpr int m1 = decltype(m)::value;
+            constexpr unsigned so = (unsigned)(m1 * NTI * 16);
+            oq[m1 % D] = ld_c128(rOut, voff_f, so);
+            cq[m1 % D] = ld_c64(rComp, voff_c, so / 2);
+          };
+          static_for<D>([&](auto m) { issue(m); });
+          static_for<N>([&](auto m) {
+            constexpr int m1 = decltype(m)::value;
+            constexpr unsigned so = (unsigned)(m1 * NTI * 16);
+            const double xr = a.scale * (double)v[m1].re;
+            const double xi = a.scale * (double)v[m1].im;
+            double sr = use_out ? oq[m1 % D].re : 0.0;
+            double si = use_out ? oq[m1 % D].im : 0.0;
+            double cr = use_comp ? (double)cq[m1 % D].re : 0.0;
+            double ci = use_comp ? (double)cq[m1 % D].im : 0.0;
+            if constexpr (m1 + D < N) issue(std::integral_constant<int, m1 + D>{});
+            neumaier(sr, cr, xr);
+            neumaier(si, ci, xi);
+            // the final value is s + c; before it, s and the compensation (a
+            // rounding-error term ~1e-16 |s|, which FP32 keeps)
+            st_c128(last_ks ? c128{sr + cr, si + ci} : c128{sr, si}, rOut, voff_f, so);
             st_c64(c64{(float)cr, (float)ci}, rComp, voff_c, so / 2);
-          }
+          });
         }
       }
     }
@@ -321,7 +420,35 @@ fused_apply_kernel(FusedArgs a) {
     const int x = b % 8, r = b / 8;
     b = x * q + (x < rem ? x : rem) + r;
   }
-  fused_item<N>(a, a.item0 + b, blockIdx.x, lds, threadIdx.x, false);
+  NoPairHook nh;
+  fused_item<N>(a, a.item0 + b, blockIdx.x, lds, threadIdx.x, false, nh);
+}
+
+// Persistent form: gridDim.x = 8 * W workgroups, one per CU, W per XCD
+// (workgroups are dispatched round-robin over the XCDs, so workgroup b runs on
+// XCD b % 8). In round r, the workgroups of XCD x take the W consecutive items
+// from r * 8W + x * W, so that an XCD holds the targets of whole k-points, and
+// keep in soft lockstep pair by pair (XcdLockstep). Workgroup b owns FP32
+// partial-sum slot b.
+template <int N, int WPE>
+__global__ void __launch_bounds__(N * N) __attribute__((amdgpu_waves_per_eu(WPE)))
+fused_lockstep_kernel(FusedArgs a, int* counters) {
+  __shared__ c64 lds[fused_lds_elems<N>()];
+  __shared__ LockstepState st;
+  const int G = gridDim.x, W = G / 8;
+  const int x = blockIdx.x % 8, rank = x * W + blockIdx.x / 8;
+  if (threadIdx.x == 0) {
+    st.cnt = counters + x * kLockstepStride;
+    st.target = 0;
+    st.live = 1;
+  }
+  XcdLockstep hook{&st};
+  for (int r = 0; r * G + rank < a.nitems; ++r) {
+    const int left = a.nitems - r * G - x * W;
+    if (threadIdx.x == 0) st.part = left < W ? left : W;
+    // the first pair's wait orders this write before every use
+    fused_item<N>(a, a.item0 + r * G + rank, blockIdx.x, lds, threadIdx.x, false, hook);
+  }
 }
 
 // Persistent workgroups of NT threads pop queue entries (cell, target, second
@@ -339,6 +466,7 @@ fused_batched_kernel(BatchArgs B) {
   static_assert(2 * fused_lds_elems<16>() <= fused_lds_elems<24>(), "two 16^3 regions must fit");
   __shared__ c64 lds[fused_lds_elems<24>()];
   __shared__ int it_sh;
+  NoPairHook nh;
   int sq = blockIdx.x % kBatchQueues;  // only thread 0 uses these two
   int tried = 0;
   for (;;) {
@@ -369,11 +497,11 @@ fused_batched_kernel(BatchArgs B) {
         const int g = tr / 256;  // groups are whole waves
         const bool second = item2 >= 0 && g == 1;
         fused_item<16>(a, second ? item2 : item, blockIdx.x, second ? lds + fused_lds_elems<16>() : lds, tr % 256,
-                       !(g == 0 || second));
+                       !(g == 0 || second), nh);
         break;
       }
-      case 20: fused_item<20>(a, item, blockIdx.x, lds, tr % 400, tr >= 400); break;
-      default: fused_item<24>(a, item, blockIdx.x, lds, tr, false); break;
+      case 20: fused_item<20>(a, item, blockIdx.x, lds, tr % 400, tr >= 400, nh); break;
+      default: fused_item<24>(a, item, blockIdx.x, lds, tr, false, nh); break;
     }
   }
 }
@@ -388,6 +516,15 @@ hipError_t launch_n(const FusedArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int N, int WPE>
+hipError_t launch_lockstep_n(const FusedArgs& a, const LockstepCfg& ls, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(1), 0, st, ls.counters, kLockstepInts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fused_lockstep_kernel<N, WPE>), dim3(ls.nwg), dim3(N * N), 0, st, a, ls.counters);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 size_t fused_acc_scratch_elems(int n, int nslots) {
@@ -397,14 +534,19 @@ size_t fused_acc_scratch_elems(int n, int nslots) {
   }
 }
 
-int fused_variants(int n) { return (n == 16 || n == 20) ? 2 : 1; }
+int fused_variants(int n) { return (n == 16 || n == 20 || n == 32) ? 2 : 1; }
 
-hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant) {
+bool fused_has_lockstep(int n) { return n == 32; }
+
+hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant, const LockstepCfg* ls) {
   switch (n) {
     case 16: return variant == 1 ? launch_n<16, 2>(a, st) : launch_n<16, 4>(a, st);
     case 20: return variant == 1 ? launch_n<20, 2>(a, st) : launch_n<20, 4>(a, st);
     case 24: return launch_n<24, 3>(a, st);
-    case 32: return launch_n<32, 4>(a, st);
+    case 32:
+      if (variant != 1) return launch_n<32, 4>(a, st);
+      if (!ls || !ls->counters || ls->nwg < 8 || ls->nwg % 8 != 0) return hipErrorInvalidValue;
+      return launch_lockstep_n<32, 4>(a, *ls, st);
     default: return hipErrorInvalidValue;
   }
 }

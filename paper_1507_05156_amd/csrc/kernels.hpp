@@ -53,8 +53,22 @@ struct FusedArgs {
   int xcd_map;        // 1: map workgroups so that one XCD runs the targets of one k
   int n;              // grid length of this cell (batched launch)
 };
-// n in {16, 20, 24, 32}; variant < fused_variants(n) selects the register/occupancy target
-hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant = 0);
+// Persistent lockstep form of the fused kernel, for grid lengths whose FP32
+// partial sums live in global memory: nwg workgroups (a multiple of 8, at most
+// one per CU) keep pace with the other workgroups of their XCD pair by pair.
+// counters: kLockstepInts ints of caller-owned device memory, cleared by the
+// launch.
+constexpr int kLockstepStride = 32;  // ints between the XCD counters (128 bytes)
+constexpr int kLockstepInts = 8 * kLockstepStride;
+struct LockstepCfg {
+  int* counters;
+  int nwg;
+};
+bool fused_has_lockstep(int n);
+// n in {16, 20, 24, 32}; variant < fused_variants(n) selects the register/occupancy
+// target, or (the last variant where fused_has_lockstep(n)) the lockstep form, which needs ls
+hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant = 0,
+                              const LockstepCfg* ls = nullptr);
 int fused_variants(int n);
 size_t fused_acc_scratch_elems(int n, int nslots);  // c64 elements needed in accs (0 if registers)
 
