@@ -32,13 +32,14 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
 # the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "10b79d616fc0959b89b97bb6b59527ab70439abc101ed8a9dca5341ebfade9d8",
+    "sources_sha256": "4a5596bae04f970d8869a0b0cc8e5be978fa078a13b51a5636c99fdd962be301",
     "workload": 2,
-    "fetch_kib": 6339252342.625, "write_kib": 3773192262.5625,
-    "fetch_scale": 1.999886995978821, "write_scale": 1.0,
+    "fetch_kib": 3696361277.53125, "write_kib": 3822939670.6875,
+    "fetch_scale": 1.9998838968923347, "write_scale": 1.0,
 }
 KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/fft_reg.hpp",
-                  "paper_1507_05156_amd/csrc/kernels.hpp")
+                  "paper_1507_05156_amd/csrc/fused_common.hpp", "paper_1507_05156_amd/csrc/kernels.hpp",
+                  "paper_1507_05156_amd/csrc/plan.hpp", "paper_1507_05156_amd/csrc/api.hip")
 
 
 def kernel_sources_digest() -> str:
