@@ -39,3 +39,4 @@ from .fock import (fock_apply, pair_potential, exchange_energy, exchange_energy_
 from .adjoint import fock_vjp, energy_grad  # noqa: F401
 from .ortho import gram_schmidt  # noqa: F401
 from . import taylor  # noqa: F401
+from . import excited  # noqa: F401

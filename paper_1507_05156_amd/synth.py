@@ -1,8 +1,8 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the smoke run.
 
-This module draws the inputs only: lattice, k-mesh and orbitals. It contains
-none of the exchange operator's arithmetic, so both the HIP path and the CPU
-oracle may take their inputs from it.
+This module draws the inputs only: lattice, k-mesh, orbitals and a model local
+potential. It contains none of the exchange operator's arithmetic, so both the
+HIP path and the CPU oracle may take their inputs from it.
 
 Workload recipe (stand-in for the paper's silicon ground-state orbitals, which
 need pseudopotential data that is not available):
@@ -138,6 +138,37 @@ WORKLOADS = {
     3: dict(n=24, nk=4, nb=16),
     4: [dict(n=16, nk=3, nb=8), dict(n=20, nk=4, nb=12), dict(n=24, nk=5, nb=16)],
 }
+
+
+# Empirical local pseudopotential of bulk silicon (Cohen and Bergstresser,
+# Phys. Rev. 141, 789 (1966)): symmetric form factors in Rydberg at
+# |G|^2 = 3, 8, 11 in units of (2 pi / a)^2, diamond structure with the two
+# atoms of each primitive cell at +-tau, tau = (a/8)(1, 1, 1).
+SI_FORM_FACTORS_RY = {3: -0.21, 8: 0.04, 11: 0.08}
+
+
+def model_vloc(n) -> np.ndarray:
+    """A crystal-like local potential v[n1][n2][n3] (Ha) on the grid of the cubic
+    8-atom silicon cell (any side a): v(r) = sum_G V(|G|^2) cos(G.tau) cos(G.r)
+    over the G = (2 pi / a)(h, k, l) with |G|^2 in the form-factor table. With it the
+    lowest 16 bands of T + v_loc are separated from the 17th by a gap of about
+    1 eV, as for the valence bands of silicon, so that the occupied subspace
+    of the Hamiltonian is well defined (the random orbitals alone give nearly
+    free-electron shells)."""
+    n1, n2, n3 = (int(n), int(n), int(n)) if np.isscalar(n) else tuple(int(x) for x in n)
+    m1, m2, m3 = np.meshgrid(np.arange(n1) / n1, np.arange(n2) / n2, np.arange(n3) / n3, indexing="ij")
+    v = np.zeros((n1, n2, n3))
+    rng3 = range(-3, 4)
+    for h in rng3:
+        for k in rng3:
+            for l in rng3:
+                g2 = h * h + k * k + l * l
+                if g2 not in SI_FORM_FACTORS_RY or not (h % 2 == k % 2 == l % 2):
+                    continue
+                structure = np.cos(np.pi / 4.0 * (h + k + l))          # G . tau
+                phase = 2.0 * np.pi * (h * m1 + k * m2 + l * m3)       # G . r on the grid
+                v += 0.5 * SI_FORM_FACTORS_RY[g2] * structure * np.cos(phase)
+    return v
 
 
 def random_fields(shape, seed, dtype=np.complex128) -> np.ndarray:
