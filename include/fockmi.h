@@ -41,6 +41,7 @@ typedef struct fockmi_plan_s* fockmi_plan;
 typedef enum {
   FOCK_OK = 0,
   FOCK_WARN_NORM = 1,    /* taylor_step: norm drift above the plan threshold (psi still written) */
+  FOCK_WARN_CONV = 2,    /* fock_eigensolve: maxit reached above tol (the current vectors still written) */
   FOCK_ERR_ARG = -1,     /* null / misaligned pointer, bad index, aliasing, bad scalar */
   FOCK_ERR_SIZE = -2,    /* grid length outside {16, 20, 24, 32}, or a form that needs a cubic grid */
   FOCK_ERR_HIP = -3,     /* a HIP runtime call failed (message in fock_last_error) */
@@ -167,6 +168,40 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
  * inner product (Omega/N_r) sum conj(a) b (the normalisation that Eq. (15)
  * assumes for occupied orbitals). psi: device [nk][nb][N_r] complex128 in place. */
 fock_status fock_orthonormalize(fockmi_plan plan, int cell, void* psi, void* stream);
+
+/* Eigenstates of the Hamiltonian after the pulse (Sec. IV B, Eq. (25)): the nb
+ * lowest eigenpairs, at every k, of
+ *   h_k = IDFT(|k+G+A/c|^2/2 DFT .) + v_loc + alpha * V_x[u_occ]
+ * (the propagator's h with the Fock-like term built from u_occ and held fixed),
+ * by block LOBPCG in FP64 with a kinetic preconditioner.
+ *   u_occ    : device [nk][nb][N_r] complex128, the orbitals that build V_x
+ *   vloc     : device [N_r] float64 local potential, or NULL
+ *   A_over_c : host [3] A/c (bohr^-1)
+ *   phi      : device [nk][nb][N_r] complex128, in: a starting block of full rank
+ *              (u_occ itself is a natural one), out: the eigenvectors in ascending
+ *              order, (Omega/N_r) sum conj(phi_i) phi_j = delta_ij; must not alias u_occ
+ *   tol      : stop when every residual (Omega/N_r)^(1/2) ||h phi - eps phi|| <= tol
+ *   maxit    : iteration limit (each iteration applies h once to nb vectors per k)
+ *   eig_host : host [nk][nb] <- eigenvalues (Ha), may be NULL
+ *   res_host : host [nk][nb] <- final residual norms, may be NULL
+ *   iters_host : host <- iterations taken, may be NULL
+ * At most 16 bands per k (FOCK_ERR_SIZE otherwise). Synchronises the stream
+ * once per iteration. Returns FOCK_WARN_CONV when maxit ends the iteration
+ * above tol. The eigenvectors are unique up to phases where the eigenvalues
+ * are; the span of all nb is unique when h has a gap above the nb-th. */
+fock_status fock_eigensolve(fockmi_plan plan, int cell, const void* u_occ, const double* vloc,
+                            const double A_over_c[3], double alpha, void* phi, double tol, int maxit,
+                            double* eig_host, double* res_host, int* iters_host, void* stream);
+
+/* Number density of excited electrons (Sec. IV B, Eq. (26)), with the k-point
+ * sum written out:
+ *   n_ex = (g_s / (N_k Omega)) sum_k [ nb - sum_{i,j} |<phi_ik | psi_jk>|^2 ],
+ *   <a|b> = (Omega/N_r) sum_r conj(a) b,
+ * phi the eigenvectors of fock_eigensolve (orthonormal), psi the time-dependent
+ * orbitals, both device [nk][nb][N_r] complex128. *nex_host <- n_ex (bohr^-3).
+ * FP64 with a fixed-order reduction; synchronises the stream. */
+fock_status fock_excited_density(fockmi_plan plan, int cell, const void* phi, const void* psi, double* nex_host,
+                                 void* stream);
 
 /* All cells of the plan in one persistent launch (FOCK_FP32_COMP plans with up
  * to 8 cells of grid lengths 16, 20, 24, none down-sampled), replayed from a

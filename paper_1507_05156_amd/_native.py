@@ -14,12 +14,13 @@ LIB_PATH = os.path.join(HERE, "libfockmi.so")
 
 FOCK_OK = 0
 FOCK_WARN_NORM = 1
+FOCK_WARN_CONV = 2
 FOCK_ERR_ARG = -1
 FOCK_ERR_SIZE = -2
 FOCK_ERR_HIP = -3
 FOCK_ERR_NOMEM = -4
 FOCK_ERR_STATE = -5
-STATUS_NAMES = {0: "FOCK_OK", 1: "FOCK_WARN_NORM", -1: "FOCK_ERR_ARG", -2: "FOCK_ERR_SIZE", -3: "FOCK_ERR_HIP",
+STATUS_NAMES = {0: "FOCK_OK", 1: "FOCK_WARN_NORM", 2: "FOCK_WARN_CONV", -1: "FOCK_ERR_ARG", -2: "FOCK_ERR_SIZE", -3: "FOCK_ERR_HIP",
                 -4: "FOCK_ERR_NOMEM", -5: "FOCK_ERR_STATE"}
 
 FOCK_FP64 = 0
@@ -27,7 +28,8 @@ FOCK_FP32_COMP = 1
 FOCK_FP64_FUSED = 2
 
 EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_energy", "fock_vjp", "taylor_step",
-           "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_apply_batched", "fock_profile_enable",
+           "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_eigensolve",
+           "fock_excited_density", "fock_apply_batched", "fock_profile_enable",
            "fock_profile_read", "fock_last_error"]
 
 
@@ -66,6 +68,8 @@ def lib():
     L.taylor_step_vjp.argtypes = [vp, i, vp, vp, pd, d, d, i, vp, vp, pd, vp]
     L.taylor_energy.argtypes = [vp, i, vp, vp, pd, d, pd, vp, pd, vp]
     L.fock_orthonormalize.argtypes = [vp, i, vp, vp]
+    L.fock_eigensolve.argtypes = [vp, i, vp, vp, pd, d, vp, d, i, pd, pd, C.POINTER(i), vp]
+    L.fock_excited_density.argtypes = [vp, i, vp, vp, pd, vp]
     L.fock_apply_batched.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i), C.POINTER(vp), vp]
     L.fock_profile_enable.argtypes = [vp, i]
     L.fock_profile_read.argtypes = [vp, pd, C.POINTER(C.c_longlong), i]

@@ -221,6 +221,36 @@ class Plan:
         N.check(self._lib.fock_orthonormalize(self._h, cell, _ptr(psi), _stream()))
         return psi
 
+    def eigensolve(self, u, phi=None, vloc=None, a_over_c=(0.0, 0.0, 0.0), alpha=0.25, tol=1e-8, maxit=200, cell=0):
+        """The nb lowest eigenpairs of h = T[A/c] + v_loc + alpha V_x[u] at every k (Eq. (25)).
+
+        phi: starting block (default: a copy of u); returns (phi, eigenvalues [nk][nb],
+        residual norms [nk][nb], iterations, converged)."""
+        c = self.cells[cell]
+        self._check(u, cell, c["nb"], "u")
+        phi = u.clone() if phi is None else phi
+        self._check(phi, cell, c["nb"], "phi")
+        av = (C.c_double * 3)(*[float(x) for x in a_over_c])
+        nkb = c["nk"] * c["nb"]
+        ev = (C.c_double * nkb)()
+        rs = (C.c_double * nkb)()
+        it = C.c_int()
+        st = N.check(self._lib.fock_eigensolve(self._h, cell, _ptr(u), _ptr(vloc) if vloc is not None else None, av,
+                                               float(alpha), _ptr(phi), float(tol), int(maxit), ev, rs,
+                                               C.byref(it), _stream()))
+        shape = (c["nk"], c["nb"])
+        return (phi, np.array(ev[:]).reshape(shape), np.array(rs[:]).reshape(shape), it.value,
+                st == N.FOCK_OK)
+
+    def excited_density(self, phi, psi, cell=0):
+        """n_ex of Eq. (26) (bohr^-3) for eigenvectors phi and orbitals psi."""
+        c = self.cells[cell]
+        self._check(phi, cell, c["nb"], "phi")
+        self._check(psi, cell, c["nb"], "psi")
+        out = C.c_double()
+        N.check(self._lib.fock_excited_density(self._h, cell, _ptr(phi), _ptr(psi), C.byref(out), _stream()))
+        return out.value
+
     def apply_batched(self, us, phis=None):
         """All cells in one persistent launch: returns [V_x[u_c] phi_c for each cell c]."""
         nc = len(self.cells)

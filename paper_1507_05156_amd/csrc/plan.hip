@@ -208,6 +208,7 @@ void Plan::destroy() {
                     &red6, &vloc_buf, &sync})
     b->release();
   bstate.release();
+  eig.release();
   if (host_pinned) (void)hipHostFree(host_pinned);
   host_pinned = nullptr;
   magic = 0;

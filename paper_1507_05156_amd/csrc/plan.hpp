@@ -79,6 +79,13 @@ struct BatchState {
   void release();
 };
 
+// work arrays of the block eigensolver (eig_api.hip)
+struct EigState {
+  DevBuf x, hx, w, hw, p, hp, xn, hxn, pn, hpn;  // [nk][nb][N_r] blocks and their images under h
+  DevBuf S, A, C, lam, status;                    // Rayleigh-Ritz matrices, coefficients, values, flags
+  void release();
+};
+
 struct Plan {
   static constexpr unsigned kMagic = 0xF0C4C0DEu;
   unsigned magic = kMagic;
@@ -104,6 +111,7 @@ struct Plan {
   bool tuning = false;
   int use_graph = 1;
   BatchState bstate;
+  EigState eig;
   int num_cus = 0;
 
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -147,6 +155,11 @@ struct Plan {
   // max over (k, b) of |(Omega/N_r) ||psi_kb||^2 - 1|; synchronises st
   fock_status norm_dev(Cell& c, const c128* psi, hipStream_t st, double* dev);
   fock_status field_bufs(Cell& c, std::initializer_list<DevBuf*> bufs, int nfields_per_k);
+
+  // eigenstates of h (Eq. (25)) and the excited-electron density (Eq. (26)) (eig_api.hip)
+  fock_status eigensolve(Cell& c, const c128* u, c128* phi, const double* vloc, const double a[3], double alpha,
+                         double tol, int maxit, double* eig_host, double* res_host, int* iters_host, hipStream_t st);
+  fock_status excited_density(Cell& c, const c128* phi, const c128* psi, hipStream_t st, double* nex);
 
   // batched persistent launch (batched.hip)
   fock_status run_batched(const void* const* u, const void* const* phi, const int* nphi, void* const* vphi,

@@ -40,6 +40,24 @@ __global__ void kinetic_mul_kernel(c128* __restrict__ F, const double* __restric
   F[(long)field * nr + l] = v;
 }
 
+// F[k][f][l] *= scale / (1 + |k + G_l + a|^2 / (2 e0)): the kinetic preconditioner
+// of the block eigensolver, damping the plane waves far above the energy e0
+__global__ void precond_mul_kernel(c128* __restrict__ F, const double* __restrict__ kpts, int nf, Geom g, double a0,
+                                   double a1, double a2, double e0, double scale) {
+  const long nr = (long)g.n1 * g.n2 * g.n3;
+  const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int field = blockIdx.y;
+  if (l >= nr) return;
+  const int k = field / nf;
+  double p[3];
+  gvec(g, l, kpts[3 * k], kpts[3 * k + 1], kpts[3 * k + 2], a0, a1, a2, p);
+  const double f = scale / (1.0 + 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) / e0);
+  c128 v = F[(long)field * nr + l];
+  v.re *= f;
+  v.im *= f;
+  F[(long)field * nr + l] = v;
+}
+
 // out = (base ? base : 0) + c * (kin + vloc .* x + alpha * vx)
 __global__ void hcombine_kernel(c128* __restrict__ out, const c128* __restrict__ base, const c128* __restrict__ kin,
                                 const c128* __restrict__ x, const c128* __restrict__ vx,
@@ -204,6 +222,14 @@ hipError_t launch_kinetic_mul(c128* F, const double* kpts, int nk, int nf, const
   const long nr = (long)g.n1 * g.n2 * g.n3;
   dim3 grid((unsigned)((nr + 255) / 256), (unsigned)(nk * nf));
   hipLaunchKernelGGL(kinetic_mul_kernel, grid, dim3(256), 0, st, F, kpts, nf, g, a[0], a[1], a[2], scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_mul(c128* F, const double* kpts, int nk, int nf, const Geom& g, const double a[3],
+                              double e0, double scale, hipStream_t st) {
+  const long nr = (long)g.n1 * g.n2 * g.n3;
+  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)(nk * nf));
+  hipLaunchKernelGGL(precond_mul_kernel, grid, dim3(256), 0, st, F, kpts, nf, g, a[0], a[1], a[2], e0, scale);
   return hipGetLastError();
 }
 

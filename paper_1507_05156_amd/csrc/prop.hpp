@@ -8,6 +8,9 @@ namespace fockmi {
 // F[k][f][l] *= scale * |k + G_l + a|^2 / 2 for nk x nf Fourier-space fields
 hipError_t launch_kinetic_mul(c128* F, const double* kpts, int nk, int nf, const Geom& g, const double a[3],
                               double scale, hipStream_t st);
+// F *= scale / (1 + |k + G + a|^2 / (2 e0)) in Fourier space (eigensolver preconditioner)
+hipError_t launch_precond_mul(c128* F, const double* kpts, int nk, int nf, const Geom& g, const double a[3],
+                              double e0, double scale, hipStream_t st);
 // out = (base ? base : 0) + (cre + i cim) * (kin + vloc .* x + alpha * vx); vloc / vx may be NULL
 hipError_t launch_hcombine(c128* out, const c128* base, const c128* kin, const c128* x, const c128* vx,
                            const double* vloc, double alpha, double cre, double cim, long count, int nr,

@@ -1,0 +1,116 @@
+"""Eigenstates of h(t_f) and the excited-electron density (Sec. IV B, Eqs. (25)-(26))
+through the C ABI, against the FP64 oracle's dense values (tests/golden), its
+matrix-free Hamiltonian and closed forms."""
+
+import importlib.util
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import excited, lattice
+from paper_1507_05156_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OMEGA = synth.OMEGA_HSE
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def golden():
+    spec = importlib.util.spec_from_file_location("make_excited", os.path.join(HERE, "golden", "make_excited_16cube.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(HERE, "golden", "excited_16cube.json")) as f:
+        return mod, json.load(f)
+
+
+def plan_for(cell, kp, nb, n=16):
+    from paper_1507_05156_amd.api import Plan
+    return Plan(dict(n=n, a=cell, kpts=kp, nb=nb, omega=OMEGA), prec="fp64")
+
+
+def test_eigenstates_and_density_match_dense_oracle(device):
+    """16^3, 2 k-points, 16 bands, silicon model potential, alpha = 1/4, A/c != 0."""
+    print("[gpu] eigensolve 16^3 vs golden", flush=True)
+    mod, g = golden()
+    case = g["case"]
+    cell, kp, psi, v = mod.inputs(case)
+    nb = case["nb"]
+    avec = np.array(case["a_over_c"])
+    plan = plan_for(cell, kp, nb)
+    phi, eps, res, iters, conv = plan.eigensolve(to_dev(psi), vloc=to_dev(v), a_over_c=avec, alpha=case["alpha"],
+                                                 tol=1e-10, maxit=400)
+    print(f"  iterations {iters}, max residual {res.max():.2e}", flush=True)
+    assert conv and res.max() <= 1e-10
+    ref = np.array(g["eigenvalues"])[:, :nb]
+    err = np.max(np.abs(eps - ref))
+    print(f"  eigenvalues max abs err {err:.2e}", flush=True)
+    assert err < 1e-9
+    phin = phi.cpu().numpy()
+    # the oracle's own operator and inner product
+    r = excited.residuals_matfree(psi, phin, eps, kp, cell, OMEGA, avec, case["alpha"], vloc=v)
+    assert r.max() < 1e-8, r.max()
+    S = excited.overlaps(phin, phin, cell)
+    assert max(np.max(np.abs(S[k] - np.eye(nb))) for k in range(len(kp))) < 1e-12
+    nex = plan.excited_density(phi, to_dev(psi))
+    rel = abs(nex - g["n_ex"]) / g["n_ex"]
+    print(f"  n_ex {nex:.12e} vs {g['n_ex']:.12e} (rel {rel:.1e})", flush=True)
+    assert rel < 1e-6
+
+
+def test_density_kernel_matches_the_formula(device):
+    """n_ex for arbitrary orthonormal phi and orbitals psi against the oracle's formula."""
+    print("[gpu] excited density kernel", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell)
+    phi = synth.orbitals(16, cell, kp, 5, seed=61)
+    psi = synth.orbitals(16, cell, kp, 5, seed=62)
+    psi = 0.8 * phi + 0.6 * psi  # partly inside span(phi)
+    plan = plan_for(cell, kp, 5)
+    got = plan.excited_density(to_dev(phi), to_dev(psi))
+    ref = excited.excited_density(phi, psi, cell)
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+    assert abs(plan.excited_density(to_dev(phi), to_dev(phi))) < 1e-14
+
+
+def test_free_electron_eigenvalues(device):
+    """alpha = 0 and no local potential: the eigenvalues are the lowest |k+G+a|^2/2."""
+    print("[gpu] eigensolve free electrons", flush=True)
+    cell = synth.cubic_cell()
+    kp = np.array([[0.05, -0.11, 0.17], [0.21, 0.02, -0.08]])
+    avec = np.array([0.01, 0.0, -0.03])
+    u = synth.orbitals(16, cell, kp, 4, seed=63)
+    plan = plan_for(cell, kp, 4)
+    _, eps, res, iters, conv = plan.eigensolve(to_dev(u), alpha=0.0, a_over_c=avec, tol=1e-10, maxit=400)
+    assert conv
+    G = lattice.gvectors((16, 16, 16), lattice.reciprocal(cell)).reshape(-1, 3)
+    for k in range(2):
+        ref = np.sort(0.5 * np.sum((G + kp[k] + avec) ** 2, axis=1))[:4]
+        assert np.max(np.abs(eps[k] - ref)) < 1e-10, (k, eps[k], ref)
+
+
+def test_iteration_limit_and_bad_arguments(device):
+    print("[gpu] eigensolve limits", flush=True)
+    from paper_1507_05156_amd._native import FockError
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(16, cell, kp, 4, seed=64)
+    plan = plan_for(cell, kp, 4)
+    v = to_dev(synth.model_vloc(16))
+    _, _, res, iters, conv = plan.eigensolve(to_dev(u), vloc=v, tol=1e-12, maxit=1)
+    assert not conv and iters == 1 and res.max() > 1e-12
+    ud = to_dev(u)
+    with pytest.raises(FockError):
+        plan.eigensolve(ud, phi=ud)  # phi aliases u
+    with pytest.raises(FockError):
+        plan.eigensolve(ud, tol=-1.0)
+    big = plan_for(cell, kp, 17)
+    with pytest.raises(FockError):
+        big.eigensolve(to_dev(synth.orbitals(16, cell, kp, 17, seed=65)))
