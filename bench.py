@@ -98,8 +98,9 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     launched one by one, and against the plain FP64 path for the error), the FP64
     adjoint and Taylor-4 step at 24^3 / 64 k / 16 bands, and E_x (FP32 form) and
     the FP64 orthonormalisation on the bench workload, the down-sampled sum as
-    the paper runs it (12^3 k-points, 4^3 source sub-mesh, 16 bands), and the
-    work of the field against the energy functional at two time steps."""
+    the paper runs it (12^3 k-points, 4^3 source sub-mesh, 16 bands), the
+    work of the field against the energy functional at two time steps, and the
+    eigenstates after a pulse with the excited-electron density."""
     out = {}
     # ------------------------------------------- batched persistent launch (three cells)
     cells, us = [], []
@@ -223,6 +224,36 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
             "extrapolated_E_ex": 2 * e2 - e1, "extrapolated_Omega_W": 2 * w2 - w1}
     out["work_vs_energy_16cube_8k_4b"] = leg
     del pw, u
+    # ------------- excited electrons after a pulse (Sec. IV B, Eqs. (25)-(26)): 16^3, 8 k, 16 bands
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell)
+    u = torch.from_numpy(synth.orbitals(16, cell, kp, 16, seed=synth.seed_for(7, 0))).to(dev)
+    v = torch.from_numpy(synth.model_vloc(16)).to(dev)
+    px = Plan(dict(n=16, a=cell, kpts=kp, nb=16, omega=omega), prec="fp64f")
+    px.eigensolve(u, vloc=v, tol=1e-4, maxit=5)  # warm-up (allocations, tables)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi0, eps0, res0, it0, conv0 = px.eigensolve(u, vloc=v, alpha=0.25, tol=1e-8, maxit=400)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    leg = {"setting": "silicon model potential, alpha = 1/4, FP64 fused form; psi(0) = the 16 lowest states of "
+                      "h[u] for seeded orbitals u; 40 Taylor steps of dt = 0.02 under the 1.55 eV pulse; "
+                      "eigenstates of h(t_f) from psi(t_f), tol 1e-8",
+           "eigensolve_ms": t_eig * 1e3, "eigensolve_iterations": it0, "eigensolve_converged": conv0,
+           "ms_per_iteration": t_eig * 1e3 / max(it0, 1), "pairs_per_h_application": (len(kp) * 16) ** 2,
+           "valence_density": 2.0 * 16 / abs(np.linalg.det(cell))}
+    for A0 in (0.0, 0.5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nex, _, it, conv, _, _ = dynamics.excited_density_after_pulse(px, psi0, A0, 0.02, 40, vloc=v, tol=1e-8)
+        torch.cuda.synchronize()
+        leg[f"A0_{A0}"] = {"n_ex": nex, "eigensolve_iterations": it, "converged": conv,
+                           "seconds_propagation_and_eigensolve": time.perf_counter() - t0}
+    out["excited_16cube_8k_16b"] = leg
+    print(f"[bench] excited density 16^3/8k/16b: eigensolve {t_eig * 1e3:.0f} ms ({it0} iterations), "
+          f"n_ex {leg['A0_0.0']['n_ex']:.3e} (no pulse) / {leg['A0_0.5']['n_ex']:.3e} (A0 = 0.5)",
+          file=sys.stderr, flush=True)
+    del px, u, v, psi0
     # ------------------------------------- E_x and orthonormalisation, the bench workload
     t_e = _timed(lambda: plan32_c2.energy(ud_c2), 1, torch)
     psi = ud_c2.clone()

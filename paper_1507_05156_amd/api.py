@@ -230,6 +230,9 @@ class Plan:
         self._check(u, cell, c["nb"], "u")
         phi = u.clone() if phi is None else phi
         self._check(phi, cell, c["nb"], "phi")
+        if vloc is not None:
+            if vloc.dtype != torch.float64 or not vloc.is_cuda or vloc.numel() != c["nr"] or not vloc.is_contiguous():
+                raise ValueError("vloc must be a contiguous float64 CUDA tensor with N_r entries")
         av = (C.c_double * 3)(*[float(x) for x in a_over_c])
         nkb = c["nk"] * c["nb"]
         ev = (C.c_double * nkb)()

@@ -60,3 +60,21 @@ def work_and_energy(plan, psi0, A0, dt, nsteps, alpha=0.25, omega_l=0.0569614, v
     e0 = plan.energy_functional(psi0, pulse_a_over_c(0.0, A0, omega_l, Td, direction), alpha, vloc=vloc, cell=cell)
     eN = plan.energy_functional(psi, pulse_a_over_c(Td, A0, omega_l, Td, direction), alpha, vloc=vloc, cell=cell)
     return eN - e0, vol * w, np.array(js)
+
+
+def excited_density_after_pulse(plan, psi0, A0, dt, nsteps, alpha=0.25, omega_l=0.0569614, vloc=None,
+                                direction=(0.0, 0.0, 1.0), tol=1e-8, maxit=400, cell=0):
+    """Propagate psi0 through nsteps Taylor steps under the pulse (T_d = nsteps dt), then
+    take the eigenstates of h(t_f) (Sec. IV B, Eq. (25); V_x built from psi(t_f), A(t_f))
+    starting from psi(t_f), and n_ex of Eq. (26).
+
+    Returns (n_ex, eigenvalues [nk][nb], iterations, converged, psi(t_f), phi)."""
+    psi = psi0.clone()
+    Td = nsteps * dt
+    for n in range(nsteps):
+        plan.taylor_step(psi, pulse_a_over_c(n * dt, A0, omega_l, Td, direction), dt, alpha, vloc=vloc, cell=cell,
+                         want_norm=False)
+    a_f = pulse_a_over_c(Td, A0, omega_l, Td, direction)
+    phi, eps, _, it, conv = plan.eigensolve(psi, phi=psi.clone(), vloc=vloc, a_over_c=a_f, alpha=alpha, tol=tol,
+                                            maxit=maxit, cell=cell)
+    return plan.excited_density(phi, psi, cell=cell), eps, it, conv, psi, phi
