@@ -214,7 +214,8 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   a.accumulate = accumulate ? 1 : 0;
   a.xcd_map = xcd_map;
   a.n = c.geom.n1;
-  int variant = (c.geom.n1 == 32 && has_ls) ? fused32_variant : 0;
+  int variant = fused_default_variant(c.geom.n1);
+  if (variant >= nvar) variant = 0;
   hipError_t e;
   const std::string key = key_for(c, ps, nx, "fused");
   TuneEntry te;

@@ -65,6 +65,7 @@ struct LockstepCfg {
   int nwg;
 };
 bool fused_has_lockstep(int n);
+int fused_default_variant(int n);  // the variant used when no tuned choice exists
 // n in {16, 20, 24, 32}; variant < fused_variants(n) selects the register/occupancy
 // target, or (the last variant where fused_has_lockstep(n)) the lockstep form, which needs ls
 hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant = 0,

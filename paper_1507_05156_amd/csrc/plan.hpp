@@ -99,9 +99,6 @@ struct Plan {
   DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres, srcbuf, srcout;
   DevBuf psi0, phiA, phiB, predb, srcbuf2, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
   DevBuf sync;                              // lockstep counters of the persistent fused form
-  // fused-kernel variant where no tuned choice exists; at 32^3 the persistent
-  // lockstep form (1) or one workgroup per target (0)
-  int fused32_variant = 1;
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
   bool profiling = false;
