@@ -183,15 +183,30 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     return s;
   }
   const int nitems = ps.ntk * nx;
-  if ((s = comp.ensure((size_t)nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
-    return s;
   // the lockstep form runs one workgroup per CU (a multiple of 8: one share per XCD)
   LockstepCfg ls{nullptr, (num_cus / 8) * 8};
   const bool has_ls = fused_has_lockstep(c.geom.n1) && ls.nwg >= 8;
+  // its k' split: the part count (dividing the source k-points, at most 4) with
+  // the fewest rounds of ls.nwg workgroups, in units of a whole target's sum
+  int ksplit = 1;
   if (has_ls) {
     if ((s = sync.ensure(kLockstepInts * sizeof(int), workspace_cap, "lockstep counters")) != FOCK_OK) return s;
     ls.counters = (int*)sync.ptr;
+    double best = 1e300;
+    for (int h = 1; h <= 4; ++h) {
+      if (ps.nsk % h) continue;
+      const double rounds = std::ceil((double)nitems * h / ls.nwg) / h;
+      if (rounds < best * (1.0 - 1e-9)) {
+        best = rounds;
+        ksplit = h;
+      }
+    }
   }
+  if ((s = comp.ensure((size_t)ksplit * nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
+    return s;
+  if (ksplit > 1 &&
+      (s = parts.ensure((size_t)(ksplit - 1) * nitems * nr * sizeof(c128), workspace_cap, "k' part sums")) != FOCK_OK)
+    return s;
   const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, std::max(nitems, ls.nwg));
   if (acc_elems && (s = accs.ensure(acc_elems * sizeof(c64), workspace_cap, "FP32 partial sums")) != FOCK_OK)
     return s;
@@ -214,6 +229,8 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   a.accumulate = accumulate ? 1 : 0;
   a.xcd_map = xcd_map;
   a.n = c.geom.n1;
+  a.ksplit = ksplit;
+  a.part_out = ksplit > 1 ? (c128*)parts.ptr : nullptr;
   int variant = fused_default_variant(c.geom.n1);
   if (variant >= nvar) variant = 0;
   hipError_t e;

@@ -141,7 +141,7 @@ struct XcdLockstep {
 // uniform over each wave.
 template <int N, class Hook>
 __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc_slot, c64* __restrict__ lds,
-                                           int t, bool twin, Hook& hook) {
+                                           int t, bool twin, Hook& hook, int part = 0) {
   constexpr int NTI = N * N;
   constexpr int NR = N * N * N;
   constexpr int NPH = fused_nph<N>();
@@ -189,18 +189,25 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   constexpr unsigned FB64 = NR * 8u;  // bytes of one complex64 field
   constexpr unsigned FB128 = NR * 16u;
 
-  const rsrc_t rX = make_rsrc(a.X + ((long)kt * a.nx + s) * NR, FB64);
-  const rsrc_t rOut = make_rsrc(a.out + ((long)kt * a.nx + s) * NR, FB128);
-  const rsrc_t rComp = make_rsrc(a.comp + ((long)kt * a.nx + s) * NR, FB64);
+  // this part's k' range and output (one part, the whole sum, unless split)
+  const long tgt = (long)kt * a.nx + s;
+  const int nkp = a.ksplit > 1 ? a.nk / a.ksplit : a.nk;
+  const int ks0 = part * nkp, ks1 = ks0 + nkp;
+  const int accumulate = part == 0 ? a.accumulate : 0;
+  c128* const outp = part == 0 ? a.out + tgt * NR : a.part_out + ((long)(part - 1) * a.nitems + tgt) * NR;
+
+  const rsrc_t rX = make_rsrc(a.X + tgt * NR, FB64);
+  const rsrc_t rOut = make_rsrc(outp, FB128);
+  const rsrc_t rComp = make_rsrc(a.comp + ((long)part * a.nitems + tgt) * NR, FB64);
   const rsrc_t rAcc = make_rsrc(ACCREG ? a.X : a.accs + (long)acc_slot * NR, ACCREG ? 0u : FB64);
 
   c64 acc[ACCREG ? N : 1];
 
-  for (int ks = 0; ks < a.nk; ++ks) {
+  for (int ks = ks0; ks < ks1; ++ks) {
     const int qi = __builtin_amdgcn_readfirstlane(a.qidx[kt * a.nk + ks]);
     const rsrc_t rK = make_rsrc(a.Kt + (long)qi * NR, NR * 4u);
-    const bool first_ks = (ks == 0);
-    const bool last_ks = (ks == a.nk - 1);
+    const bool first_ks = (ks == ks0);
+    const bool last_ks = (ks == ks1 - 1);
     for (int j = 0; j < a.nb; ++j) {
       hook(ks * a.nb + j);
       const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
@@ -346,7 +353,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
             const double xr = a.scale * (double)v[m1].re;
             const double xi = a.scale * (double)v[m1].im;
             double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-            if (!first_ks || a.accumulate) {
+            if (!first_ks || accumulate) {
               const c128 o = ld_c128(rOut, voff_f, so);
               sr = o.re;
               si = o.im;
@@ -370,7 +377,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
           // every element is loaded and stored unconditionally (the buffers are
           // whole fields) and the uniform flags only select values, so the loop
           // is straight-line code whose loads run ahead of their use
-          const bool use_out = !first_ks || a.accumulate;
+          const bool use_out = !first_ks || accumulate;
           const bool use_comp = !first_ks;
           constexpr int D = flush_depth<N>();
           c128 oq[D];
@@ -443,11 +450,28 @@ fused_lockstep_kernel(FusedArgs a, int* counters) {
     st.live = 1;
   }
   XcdLockstep hook{&st};
-  for (int r = 0; r * G + rank < a.nitems; ++r) {
-    const int left = a.nitems - r * G - x * W;
+  // work items q = part * nitems + target: equal k' ranges, so that the
+  // workgroups of one XCD-round all run the same number of pairs
+  const int h = a.ksplit > 1 ? a.ksplit : 1;
+  const int total = a.nitems * h;
+  for (int r = 0; r * G + rank < total; ++r) {
+    const int q = r * G + rank;
+    const int left = total - r * G - x * W;
     if (threadIdx.x == 0) st.part = left < W ? left : W;
     // the first pair's wait orders this write before every use
-    fused_item<N>(a, a.item0 + r * G + rank, blockIdx.x, lds, threadIdx.x, false, hook);
+    fused_item<N>(a, a.item0 + q % a.nitems, blockIdx.x, lds, threadIdx.x, false, hook, q / a.nitems);
+  }
+}
+
+// out[i] += sum_{p < nparts} parts[p][i], in that order
+__global__ void add_parts_kernel(c128* __restrict__ out, const c128* __restrict__ parts, int nparts, long count) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+    c128 v = out[i];
+    for (int p = 0; p < nparts; ++p) {
+      v.re += parts[(long)p * count + i].re;
+      v.im += parts[(long)p * count + i].im;
+    }
+    out[i] = v;
   }
 }
 
@@ -512,7 +536,9 @@ __global__ void reset_counters_kernel(int* c, int n) {
 
 template <int N, int WPE>
 hipError_t launch_n(const FusedArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((fused_apply_kernel<N, WPE>), dim3(a.nitems), dim3(N * N), 0, st, a);
+  FusedArgs b = a;
+  b.ksplit = 1;  // one workgroup per target runs the whole k' sum
+  hipLaunchKernelGGL((fused_apply_kernel<N, WPE>), dim3(b.nitems), dim3(N * N), 0, st, b);
   return hipGetLastError();
 }
 
@@ -522,6 +548,11 @@ hipError_t launch_lockstep_n(const FusedArgs& a, const LockstepCfg& ls, hipStrea
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((fused_lockstep_kernel<N, WPE>), dim3(ls.nwg), dim3(N * N), 0, st, a, ls.counters);
+  if ((e = hipGetLastError()) != hipSuccess || a.ksplit <= 1) return e;
+  const long count = (long)a.nitems * N * N * N;
+  long g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(add_parts_kernel, dim3((unsigned)g), dim3(256), 0, st, a.out, a.part_out, a.ksplit - 1, count);
   return hipGetLastError();
 }
 
@@ -550,6 +581,7 @@ hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int var
     case 32:
       if (variant != 1) return launch_n<32, 4>(a, st);
       if (!ls || !ls->counters || ls->nwg < 8 || ls->nwg % 8 != 0) return hipErrorInvalidValue;
+      if (a.ksplit > 1 && (a.item0 != 0 || a.nk % a.ksplit != 0 || !a.part_out)) return hipErrorInvalidValue;
       return launch_lockstep_n<32, 4>(a, *ls, st);
     default: return hipErrorInvalidValue;
   }

@@ -52,6 +52,11 @@ struct FusedArgs {
   int accumulate;     // 1: add to the existing out
   int xcd_map;        // 1: map workgroups so that one XCD runs the targets of one k
   int n;              // grid length of this cell (batched launch)
+  // k' split of the lockstep form (1 elsewhere): target t's sum runs as ksplit
+  // parts over equal k' ranges; part 0 writes out, part p > 0 writes FP64 field
+  // part_out[p-1][t] (t < nitems, item0 = 0), and comp holds ksplit fields per target
+  int ksplit;
+  c128* part_out;
 };
 // Persistent lockstep form of the fused kernel, for grid lengths whose FP32
 // partial sums live in global memory: nwg workgroups (a multiple of 8, at most

@@ -99,6 +99,7 @@ struct Plan {
   DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres, srcbuf, srcout;
   DevBuf psi0, phiA, phiB, predb, srcbuf2, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
   DevBuf sync;                              // lockstep counters of the persistent fused form
+  DevBuf parts;                             // FP64 part sums of the lockstep form's k' split
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
   bool profiling = false;
