@@ -253,6 +253,17 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
           f"n_ex {leg['A0_0.0']['n_ex']:.3e} (no pulse) / {leg['A0_0.5']['n_ex']:.3e} (A0 = 0.5)",
           file=sys.stderr, flush=True)
     del px, u, v, psi0
+    # ------------- one GPU's share of an 8-GPU k-point decomposition of the bench workload
+    nk2 = ud_c2.shape[0]
+    share = nk2 // 8
+    part = plan32_c2.apply_krange(ud_c2, 0, share)
+    t_share = _timed(lambda: plan32_c2.apply_krange(ud_c2, 0, share, out=part), 1, torch)
+    pairs_share = share * ud_c2.shape[1] * nk2 * ud_c2.shape[1]
+    out["shard_of_8_32cube"] = {"output_k_points": share, "pairs": pairs_share, "ms": t_share * 1e3,
+                                "pairs_per_s": pairs_share / t_share}
+    print(f"[bench] one of 8 k-point shards at 32^3 ({share} k): {t_share * 1e3:.0f} ms, "
+          f"{pairs_share / t_share:.4e} pairs/s", file=sys.stderr, flush=True)
+    del part
     # ------------------------------------- E_x and orthonormalisation, the bench workload
     t_e = _timed(lambda: plan32_c2.energy(ud_c2), 1, torch)
     psi = ud_c2.clone()

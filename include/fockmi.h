@@ -99,6 +99,21 @@ fock_status fock_plan_destroy(fockmi_plan plan);
 fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
                        void* vphi, void* stream);
 
+/* Eqs. (15)-(16) for a contiguous range of output k-points only: one GPU's
+ * share when the output k-points are divided among GPUs (every GPU needs all
+ * occupied orbitals as sources).
+ *   vphi[k][p] = (V_x[u_occ] phi)[k0 + k][p] for k < nk_out, p < nphi
+ *   u_occ : device [nk][nb][N_r] complex128, all occupied orbitals
+ *   phi   : device [nk_out][nphi][N_r] complex128, the targets at k0 .. k0 + nk_out - 1
+ *   vphi  : device [nk_out][nphi][N_r] complex128 output, overwritten; must not overlap
+ *           u_occ or phi
+ * 0 <= k0, k0 + nk_out <= nk (FOCK_ERR_ARG otherwise). Each target's sum is the
+ * one fock_apply computes; the plain FP64 path and the grid forms of the fused
+ * kernel give the same bits, the 32^3 lockstep form may group its FP64
+ * additions differently. Stream-ordered. */
+fock_status fock_apply_krange(fockmi_plan plan, int cell, const void* u_occ, int k0, int nk_out, const void* phi,
+                              int nphi, void* vphi, void* stream);
+
 /* Exchange energy of u_occ (the E_xc piece of Eq. (22)) in FP64:
  *   *ex_re, *ex_im <- E_x (the imaginary part is a check, zero in exact arithmetic).
  * Host pointers; synchronises the stream. Either output pointer may be NULL. */

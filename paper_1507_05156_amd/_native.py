@@ -27,7 +27,7 @@ FOCK_FP64 = 0
 FOCK_FP32_COMP = 1
 FOCK_FP64_FUSED = 2
 
-EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_energy", "fock_vjp", "taylor_step",
+EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_apply_krange", "fock_energy", "fock_vjp", "taylor_step",
            "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_eigensolve",
            "fock_excited_density", "fock_apply_batched", "fock_profile_enable",
            "fock_profile_read", "fock_last_error"]
@@ -61,6 +61,7 @@ def lib():
     L.fock_plan_create.argtypes = [C.POINTER(CellDesc), i, i, C.c_char_p, C.POINTER(vp)]
     L.fock_plan_destroy.argtypes = [vp]
     L.fock_apply.argtypes = [vp, i, vp, vp, i, vp, vp]
+    L.fock_apply_krange.argtypes = [vp, i, vp, i, i, vp, i, vp, vp]
     L.fock_energy.argtypes = [vp, i, vp, pd, pd, vp]
     L.fock_vjp.argtypes = [vp, i, vp, vp, i, vp, vp, vp, vp]
     L.taylor_step.argtypes = [vp, i, vp, vp, pd, d, d, i, pd, vp]

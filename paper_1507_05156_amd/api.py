@@ -125,6 +125,20 @@ class Plan:
         N.check(self._lib.fock_apply(self._h, cell, _ptr(u), _ptr(phi), phi.shape[1], _ptr(out), _stream()))
         return out
 
+    def apply_krange(self, u, k0, nk_out, phi=None, cell=0, out=None):
+        """V_x[u] phi for the output k-points k0 .. k0 + nk_out - 1 (phi: those k-points;
+        default u[k0:k0 + nk_out]); one GPU's share of a k-point decomposition."""
+        c = self.cells[cell]
+        self._check(u, cell, c["nb"], "u")
+        phi = u[k0:k0 + nk_out] if phi is None else phi
+        if not isinstance(phi, torch.Tensor) or phi.dtype != torch.complex128 or not phi.is_cuda \
+                or not phi.is_contiguous() or tuple(phi.shape[2:]) != c["n"] or phi.shape[0] != nk_out:
+            raise ValueError("phi must be a contiguous complex128 CUDA tensor [nk_out][nphi][n1][n2][n3]")
+        out = torch.empty_like(phi) if out is None else out
+        N.check(self._lib.fock_apply_krange(self._h, cell, _ptr(u), int(k0), int(nk_out), _ptr(phi), phi.shape[1],
+                                            _ptr(out), _stream()))
+        return out
+
     def energy(self, u, cell=0):
         """E_x of u as a complex number (imaginary part is a reality check)."""
         c = self.cells[cell]

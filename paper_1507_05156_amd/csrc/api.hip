@@ -345,6 +345,17 @@ fock_status Plan::sources(Cell& c, const c128* arr, int nper, DevBuf& buf, hipSt
   return FOCK_OK;
 }
 
+fock_status Plan::apply_krange(Cell& c, const c128* u, int k0, int nkout, const c128* phi, int nphi, c128* out,
+                               hipStream_t st) {
+  const c128* us = nullptr;
+  fock_status s = sources(c, u, c.nb, srcbuf, st, &us);
+  if (s != FOCK_OK) return s;
+  PairSet ps = c.fwd();  // the targets k0 .. k0 + nkout - 1: rows k0.. of the (target, source) table
+  ps.ntk = nkout;
+  ps.qidx += (size_t)k0 * ps.nsk;
+  return general(c, ps, phi, nphi, us, us, c.nb, out, -1.0 / c.nsrc, false, st);
+}
+
 fock_status Plan::apply_op(Cell& c, const c128* u, const c128* phi, int nphi, c128* out, hipStream_t st) {
   const c128* us = nullptr;
   fock_status s = sources(c, u, c.nb, srcbuf, st, &us);
@@ -449,6 +460,28 @@ fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void
   if (overlap(vphi, bp, u_occ, bu) || overlap(vphi, bp, phi, bp))
     return fail(FOCK_ERR_ARG, "vphi overlaps an input array");
   return p->apply_op(c, (const c128*)u_occ, (const c128*)phi, nphi, (c128*)vphi, (hipStream_t)stream);
+}
+
+fock_status fock_apply_krange(fockmi_plan plan, int cell, const void* u_occ, int k0, int nk_out, const void* phi,
+                              int nphi, void* vphi, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = p->check_ready(cell);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!u_occ || !phi || !vphi) return fail(FOCK_ERR_ARG, "NULL device pointer");
+  if (!aligned16(u_occ) || !aligned16(phi) || !aligned16(vphi))
+    return fail(FOCK_ERR_ARG, "device pointers must be 16-byte aligned");
+  if (nphi < 1) return fail(FOCK_ERR_ARG, "nphi must be >= 1");
+  if (k0 < 0 || nk_out < 1 || k0 + nk_out > c.nk)
+    return fail(FOCK_ERR_ARG, "k-range [%d, %d) outside the cell's %d k-points", k0, k0 + nk_out, c.nk);
+  const size_t bu = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  const size_t bp = (size_t)nk_out * nphi * c.nr * sizeof(c128);
+  if (overlap(vphi, bp, u_occ, bu) || overlap(vphi, bp, phi, bp))
+    return fail(FOCK_ERR_ARG, "vphi overlaps an input array");
+  return p->apply_krange(c, (const c128*)u_occ, k0, nk_out, (const c128*)phi, nphi, (c128*)vphi,
+                         (hipStream_t)stream);
 }
 
 fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* ex_re, double* ex_im, void* stream) {

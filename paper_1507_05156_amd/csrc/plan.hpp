@@ -136,6 +136,9 @@ struct Plan {
   // the orbitals of the source k-points, contiguous: `arr` itself without
   // down-sampling, else a copy of its S blocks ([nsrc][nper][nr]) in buf
   fock_status sources(Cell& c, const c128* arr, int nper, DevBuf& buf, hipStream_t st, const c128** out);
+  // V_x[u] phi for the output k-points k0 .. k0 + nkout - 1 only (phi, out: those k-points)
+  fock_status apply_krange(Cell& c, const c128* u, int k0, int nkout, const c128* phi, int nphi, c128* out,
+                           hipStream_t st);
   // V_x[u] phi into out (forward sums over S, weight 1/|S|)
   fock_status apply_op(Cell& c, const c128* u, const c128* phi, int nphi, c128* out, hipStream_t st);
   fock_status shadow(DevBuf& buf, const c128* src, size_t count, const char* what, hipStream_t st,
