@@ -415,7 +415,10 @@ def main():
                      "traffic_bytes_per_pair": traffic / pairs if traffic else None,
                      "traffic_GBs": traffic / kern_avg_s / 1e9 if traffic else None,
                      "valu_achieved_TFLOPs": achieved_tflops, "valu_peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
-                     "valu_frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS, "flops_per_pair": flops_per_pair(nr)},
+                     "valu_frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS,
+                     "valu_peak_unpacked_TFLOPs": FP32_VALU_PEAK_TFLOPS / 2,
+                     "valu_frac_unpacked": achieved_tflops / (FP32_VALU_PEAK_TFLOPS / 2),
+                     "flops_per_pair": flops_per_pair(nr)},
         "ffts_per_s": 2 * value,
         "fp32_repeat_bitwise_equal": repeat_equal,
         "cpu_baseline": cpu,
