@@ -82,10 +82,11 @@ def excited_density(phi, psi, a, gs=2.0):
     return gs / (nk * volume(a)) * (nk * nb - kept)
 
 
-def residuals_matfree(psi, phi, eps, kpts, a, omega, avec, alpha, vloc=None):
-    """r[k][i] = sqrt(Omega/N_r) ||h phi_ik - eps_ik phi_ik|| with the matrix-free h."""
+def residuals_matfree(psi, phi, eps, kpts, a, omega, avec, alpha, vloc=None, src=None):
+    """r[k][i] = sqrt(Omega/N_r) ||h phi_ik - eps_ik phi_ik|| with the matrix-free h
+    (V_x over the source sub-mesh src when given)."""
     phi = np.asarray(phi, dtype=np.complex128)
-    hphi = h_apply(psi, phi, kpts, a, omega, avec, alpha, vloc)
+    hphi = h_apply(psi, phi, kpts, a, omega, avec, alpha, vloc, src=src)
     nr = int(np.prod(phi.shape[-3:]))
     d = hphi - np.asarray(eps)[:, :, None, None, None] * phi
     return np.sqrt(volume(a) / nr * np.sum(np.abs(d) ** 2, axis=(2, 3, 4)))

@@ -83,6 +83,14 @@ def test_null_arguments():
     d, keep = _desc()
     assert lib.fock_plan_create(C.byref(d), 1, N.FOCK_FP64, None, None) == N.FOCK_ERR_ARG
     assert lib.fock_apply(None, 0, None, None, 1, None, None) == N.FOCK_ERR_ARG
+    assert lib.fock_apply_krange(None, 0, None, 0, 1, None, 1, None, None) == N.FOCK_ERR_ARG
+    a = (C.c_double * 3)(0.0, 0.0, 0.0)
+    it = C.c_int()
+    assert lib.fock_eigensolve(None, 0, None, None, a, 0.25, None, 1e-8, 10, None, None, C.byref(it), None) \
+        == N.FOCK_ERR_ARG
+    nex = C.c_double()
+    assert lib.fock_excited_density(None, 0, None, None, C.byref(nex), None) == N.FOCK_ERR_ARG
+    assert b"plan is NULL" in lib.fock_last_error()
     assert lib.fock_plan_destroy(None) == N.FOCK_OK
 
 
