@@ -132,21 +132,26 @@ __global__ void lock_kernel(c128* __restrict__ a, const double* __restrict__ nor
 //      its diagonal entry of the projected matrix is pushed far above the
 //      spectrum, so that it decouples and is never selected;
 //   3. M = L^-1 (D A D) L^-H, made exactly Hermitian;
-//   4. cyclic complex Jacobi on M (rotation J = diag(1, e^-i theta) R(c, s)
-//      on each pair p < q, theta the phase of M_pq), eigenvectors in V;
+//   4. parallel cyclic complex Jacobi on M (rotation J = diag(1, e^-i theta)
+//      R(c, s) on each pair p < q, theta the phase of M_pq), eigenvectors in V;
 //   5. the nsel smallest eigenvalues in ascending order, and C = D L^-H V_sel.
 // status[k] = number of dropped columns among the first nkeep.
 constexpr double kDropTol = 1e-8;
-constexpr int kEigThreads = 64;
+constexpr int kEigThreads = 256;  // four waves: one row index per lane, four pair slots
+static_assert(kEigMax <= 64, "one lane per row of the projected matrix");
 __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* __restrict__ S_, const c128* __restrict__ A_,
                                                                     int m, int nsel, int nkeep, c128* __restrict__ C_,
                                                                     double* __restrict__ lam_, int* __restrict__ status) {
-  __shared__ c128 L[kEigMax * kEigMax], M[kEigMax * kEigMax], V[kEigMax * kEigMax];
-  __shared__ double d[kEigMax], ev[kEigMax];
+  // row stride ld odd: a column access then spreads over the LDS banks instead
+  // of striking one bank per 16-byte element
+  __shared__ c128 L[kEigMax * (kEigMax + 1)], M[kEigMax * (kEigMax + 1)], V[kEigMax * (kEigMax + 1)];
+  __shared__ c128 xs[kEigMax * kRotMaxCols];  // back-substitution work
+  __shared__ double d[kEigMax], ev[kEigMax], offs[64];
   __shared__ int drop[kEigMax], order[kEigMax];
-  __shared__ double rc, rs, ere, eim, scale;
-  __shared__ int skip, done;
+  __shared__ double rcs[kEigMax / 2], rsn[kEigMax / 2], rer[kEigMax / 2], rei[kEigMax / 2], scale;
+  __shared__ int rp[kEigMax / 2], rq[kEigMax / 2], rskip[kEigMax / 2], done;
   const int k = blockIdx.x, t = threadIdx.x;
+  const int ld = m | 1;
   const c128* S = S_ + (long)k * m * m;
   const c128* A = A_ + (long)k * m * m;
 
@@ -159,38 +164,38 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
   for (int idx = t; idx < m * m; idx += kEigThreads) {
     const int i = idx / m, j = idx % m;
     const double f = d[i] * d[j];
-    L[idx] = c128{f * S[idx].re, f * S[idx].im};
-    M[idx] = c128{f * A[idx].re, f * A[idx].im};
-    V[idx] = c128{i == j ? 1.0 : 0.0, 0.0};
+    L[i * ld + j] = c128{f * S[idx].re, f * S[idx].im};
+    M[i * ld + j] = c128{f * A[idx].re, f * A[idx].im};
+    V[i * ld + j] = c128{i == j ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
 
   // Cholesky, column by column
   for (int j = 0; j < m; ++j) {
     if (t == 0) {
-      double s = L[j * m + j].re;
-      for (int p = 0; p < j; ++p) s -= L[j * m + p].re * L[j * m + p].re + L[j * m + p].im * L[j * m + p].im;
+      double s = L[j * ld + j].re;
+      for (int p = 0; p < j; ++p) s -= L[j * ld + p].re * L[j * ld + p].re + L[j * ld + p].im * L[j * ld + p].im;
       if (drop[j] || !(s > kDropTol)) {
         drop[j] = 1;
-        for (int p = 0; p < j; ++p) L[j * m + p] = c128{0.0, 0.0};
-        L[j * m + j] = c128{1.0, 0.0};
+        for (int p = 0; p < j; ++p) L[j * ld + p] = c128{0.0, 0.0};
+        L[j * ld + j] = c128{1.0, 0.0};
       } else {
-        L[j * m + j] = c128{sqrt(s), 0.0};
+        L[j * ld + j] = c128{sqrt(s), 0.0};
       }
     }
     __syncthreads();
     for (int i = j + 1 + t; i < m; i += kEigThreads) {
       if (drop[j]) {
-        L[i * m + j] = c128{0.0, 0.0};
+        L[i * ld + j] = c128{0.0, 0.0};
       } else {
-        c128 s = L[i * m + j];
+        c128 s = L[i * ld + j];
         for (int p = 0; p < j; ++p) {
-          const c128 x = cmul_(L[i * m + p], cconj(L[j * m + p]));
+          const c128 x = cmul_(L[i * ld + p], cconj(L[j * ld + p]));
           s.re -= x.re;
           s.im -= x.im;
         }
-        const double inv = 1.0 / L[j * m + j].re;
-        L[i * m + j] = c128{s.re * inv, s.im * inv};
+        const double inv = 1.0 / L[j * ld + j].re;
+        L[i * ld + j] = c128{s.re * inv, s.im * inv};
       }
     }
     __syncthreads();
@@ -199,40 +204,40 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
   if (t == 0) {
     double big = 1.0;
     for (int i = 0; i < m; ++i)
-      if (!drop[i]) big = fmax(big, fabs(M[i * m + i].re));
+      if (!drop[i]) big = fmax(big, fabs(M[i * ld + i].re));
     scale = big;
   }
   __syncthreads();
   for (int idx = t; idx < m * m; idx += kEigThreads) {
     const int i = idx / m, j = idx % m;
-    if (drop[i] || drop[j]) M[idx] = c128{(i == j) ? 1e6 * scale + i : 0.0, 0.0};
+    if (drop[i] || drop[j]) M[i * ld + j] = c128{(i == j) ? 1e6 * scale + i : 0.0, 0.0};
   }
   __syncthreads();
   // M <- L^-1 M (forward substitution, one column per thread)
   for (int c = t; c < m; c += kEigThreads) {
     for (int i = 0; i < m; ++i) {
-      c128 s = M[i * m + c];
+      c128 s = M[i * ld + c];
       for (int p = 0; p < i; ++p) {
-        const c128 x = cmul_(L[i * m + p], M[p * m + c]);
+        const c128 x = cmul_(L[i * ld + p], M[p * ld + c]);
         s.re -= x.re;
         s.im -= x.im;
       }
-      const double inv = 1.0 / L[i * m + i].re;
-      M[i * m + c] = c128{s.re * inv, s.im * inv};
+      const double inv = 1.0 / L[i * ld + i].re;
+      M[i * ld + c] = c128{s.re * inv, s.im * inv};
     }
   }
   __syncthreads();
   // M <- M L^-H (one row per thread): Z L^H = Y
   for (int r = t; r < m; r += kEigThreads) {
     for (int j = 0; j < m; ++j) {
-      c128 s = M[r * m + j];
+      c128 s = M[r * ld + j];
       for (int p = 0; p < j; ++p) {
-        const c128 x = cmul_(M[r * m + p], cconj(L[j * m + p]));
+        const c128 x = cmul_(M[r * ld + p], cconj(L[j * ld + p]));
         s.re -= x.re;
         s.im -= x.im;
       }
-      const double inv = 1.0 / L[j * m + j].re;
-      M[r * m + j] = c128{s.re * inv, s.im * inv};
+      const double inv = 1.0 / L[j * ld + j].re;
+      M[r * ld + j] = c128{s.re * inv, s.im * inv};
     }
   }
   __syncthreads();
@@ -240,79 +245,105 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
   for (int idx = t; idx < m * m; idx += kEigThreads) {
     const int i = idx / m, j = idx % m;
     if (i < j) {
-      const c128 a = M[i * m + j], b = M[j * m + i];
+      const c128 a = M[i * ld + j], b = M[j * ld + i];
       const c128 h{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
-      M[i * m + j] = h;
-      M[j * m + i] = cconj(h);
+      M[i * ld + j] = h;
+      M[j * ld + i] = cconj(h);
     } else if (i == j) {
-      M[idx].im = 0.0;
+      M[i * ld + j].im = 0.0;
     }
   }
   __syncthreads();
 
-  // cyclic Jacobi; every rotation starts behind a barrier, so that the shared
-  // rotation parameters are never rewritten while a thread still reads them
+  // parallel cyclic Jacobi: every round rotates mm/2 disjoint pairs at once (the
+  // circle method over mm = m rounded up to even; pairs with the padding index
+  // are skipped). Rotations on disjoint pairs commute, so a round equals its
+  // rotations applied one after another; a sweep of mm - 1 rounds meets every pair.
+  const int mm = m + (m & 1), npair = mm / 2;
+  const int lane = t & 63, slot = t >> 6;  // row (or column) index, pair slot
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) {
+    // largest off-diagonal modulus: per-lane maxima over rows, then one lane
+    {
       double off = 0.0;
-      for (int p = 0; p < m; ++p)
-        for (int q = p + 1; q < m; ++q) off = fmax(off, fabs(M[p * m + q].re) + fabs(M[p * m + q].im));
-      done = off <= 1e-16 * scale;
+      if (slot == 0 && lane < m)
+        for (int q = lane + 1; q < m; ++q) off = fmax(off, fabs(M[lane * ld + q].re) + fabs(M[lane * ld + q].im));
+      if (slot == 0) offs[lane] = off;  // lanes >= m hold 0
+      __syncthreads();
+      if (t == 0) {
+        double o = 0.0;
+        for (int i = 0; i < 64; ++i) o = fmax(o, offs[i]);
+        done = o <= 1e-16 * scale;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (done) break;
-    for (int p = 0; p < m - 1; ++p) {
-      for (int q = p + 1; q < m; ++q) {
-        __syncthreads();
-        if (t == 0) {
-          const c128 apq = M[p * m + q];
-          const double r = sqrt(apq.re * apq.re + apq.im * apq.im);
-          skip = !(r > 1e-18 * scale);
-          if (!skip) {
-            ere = apq.re / r;   // e^{i theta}
-            eim = apq.im / r;
-            const double tau = (M[q * m + q].re - M[p * m + p].re) / (2.0 * r);
+    for (int r = 0; r < mm - 1; ++r) {
+      // this round's pairs and their rotations, from M before the round
+      for (int i = t; i < npair; i += kEigThreads) {
+        const int a = i == 0 ? mm - 1 : (r + i) % (mm - 1);
+        const int b = i == 0 ? r : (r - i + mm - 1) % (mm - 1);
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        rp[i] = p;
+        rq[i] = q;
+        int sk = q >= m;
+        if (!sk) {
+          const c128 apq = M[p * ld + q];
+          const double rr = sqrt(apq.re * apq.re + apq.im * apq.im);
+          sk = !(rr > 1e-18 * scale);
+          if (!sk) {
+            rer[i] = apq.re / rr;  // e^{i theta}
+            rei[i] = apq.im / rr;
+            const double tau = (M[q * ld + q].re - M[p * ld + p].re) / (2.0 * rr);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            rc = 1.0 / sqrt(1.0 + tt * tt);
-            rs = tt * rc;
+            rcs[i] = 1.0 / sqrt(1.0 + tt * tt);
+            rsn[i] = tt * rcs[i];
           }
         }
-        __syncthreads();
-        if (skip) continue;  // uniform: every thread read the same flag
-        const double c = rc, s = rs, er = ere, ei = eim;
-        // columns: M <- M J, V <- V J with J = [[c, s], [-s e^{-i th}, c e^{-i th}]]
-        for (int i = t; i < m; i += kEigThreads) {
-          const c128 mp = M[i * m + p], mq = M[i * m + q];
-          const c128 mqe{mq.re * er + mq.im * ei, mq.im * er - mq.re * ei};  // mq e^{-i th}
-          M[i * m + p] = c128{c * mp.re - s * mqe.re, c * mp.im - s * mqe.im};
-          M[i * m + q] = c128{s * mp.re + c * mqe.re, s * mp.im + c * mqe.im};
-          const c128 vp = V[i * m + p], vq = V[i * m + q];
-          const c128 vqe{vq.re * er + vq.im * ei, vq.im * er - vq.re * ei};
-          V[i * m + p] = c128{c * vp.re - s * vqe.re, c * vp.im - s * vqe.im};
-          V[i * m + q] = c128{s * vp.re + c * vqe.re, s * vp.im + c * vqe.im};
-        }
-        __syncthreads();
-        // rows: M <- J^H M
-        for (int j = t; j < m; j += kEigThreads) {
-          const c128 mp = M[p * m + j], mq = M[q * m + j];
-          const c128 mqe{mq.re * er - mq.im * ei, mq.im * er + mq.re * ei};  // mq e^{+i th}
-          M[p * m + j] = c128{c * mp.re - s * mqe.re, c * mp.im - s * mqe.im};
-          M[q * m + j] = c128{s * mp.re + c * mqe.re, s * mp.im + c * mqe.im};
-        }
-        __syncthreads();
-        if (t == 0) {
-          M[p * m + q] = c128{0.0, 0.0};
-          M[q * m + p] = c128{0.0, 0.0};
-          M[p * m + p].im = 0.0;
-          M[q * m + q].im = 0.0;
-        }
+        rskip[i] = sk;
       }
+      __syncthreads();
+      // columns: M <- M J, V <- V J with J = [[c, s], [-s e^{-i th}, c e^{-i th}]] on (p, q)
+      for (int i = slot; i < npair; i += kEigThreads / 64) {
+        const int row = lane;
+        if (row >= m || rskip[i]) continue;
+        const int p = rp[i], q = rq[i];
+        const double c = rcs[i], s = rsn[i], er = rer[i], ei = rei[i];
+        const c128 mp = M[row * ld + p], mq = M[row * ld + q];
+        const c128 mqe{mq.re * er + mq.im * ei, mq.im * er - mq.re * ei};  // mq e^{-i th}
+        M[row * ld + p] = c128{c * mp.re - s * mqe.re, c * mp.im - s * mqe.im};
+        M[row * ld + q] = c128{s * mp.re + c * mqe.re, s * mp.im + c * mqe.im};
+        const c128 vp = V[row * ld + p], vq = V[row * ld + q];
+        const c128 vqe{vq.re * er + vq.im * ei, vq.im * er - vq.re * ei};
+        V[row * ld + p] = c128{c * vp.re - s * vqe.re, c * vp.im - s * vqe.im};
+        V[row * ld + q] = c128{s * vp.re + c * vqe.re, s * vp.im + c * vqe.im};
+      }
+      __syncthreads();
+      // rows: M <- J^H M
+      for (int i = slot; i < npair; i += kEigThreads / 64) {
+        const int col = lane;
+        if (col >= m || rskip[i]) continue;
+        const int p = rp[i], q = rq[i];
+        const double c = rcs[i], s = rsn[i], er = rer[i], ei = rei[i];
+        const c128 mp = M[p * ld + col], mq = M[q * ld + col];
+        const c128 mqe{mq.re * er - mq.im * ei, mq.im * er + mq.re * ei};  // mq e^{+i th}
+        M[p * ld + col] = c128{c * mp.re - s * mqe.re, c * mp.im - s * mqe.im};
+        M[q * ld + col] = c128{s * mp.re + c * mqe.re, s * mp.im + c * mqe.im};
+      }
+      __syncthreads();
+      for (int i = t; i < npair; i += kEigThreads) {
+        if (rskip[i]) continue;
+        const int p = rp[i], q = rq[i];
+        M[p * ld + q] = c128{0.0, 0.0};
+        M[q * ld + p] = c128{0.0, 0.0};
+        M[p * ld + p].im = 0.0;
+        M[q * ld + q].im = 0.0;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (t == 0) {
     for (int i = 0; i < m; ++i) {
-      ev[i] = M[i * m + i].re;
+      ev[i] = M[i * ld + i].re;
       order[i] = i;
     }
     for (int i = 0; i < nsel; ++i) {  // selection of the nsel smallest, ascending
@@ -328,22 +359,23 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
     status[k] = nd;
   }
   __syncthreads();
-  // C = D L^-H V_sel (back substitution with L^H, one selected vector per thread)
+  // C = D L^-H V_sel (back substitution with L^H, one selected vector per thread,
+  // worked in LDS and written out once)
   for (int j = t; j < nsel; j += kEigThreads) {
     const int col = order[j];
-    c128* Ck = C_ + (long)k * m * nsel;
     for (int i = m - 1; i >= 0; --i) {
-      c128 s = V[i * m + col];
+      c128 s = V[i * ld + col];
       for (int p = i + 1; p < m; ++p) {
-        const c128 x = cmul_(cconj(L[p * m + i]), Ck[p * nsel + j]);
+        const c128 x = cmul_(cconj(L[p * ld + i]), xs[p * kRotMaxCols + j]);
         s.re -= x.re;
         s.im -= x.im;
       }
-      const double inv = 1.0 / L[i * m + i].re;
-      Ck[i * nsel + j] = c128{s.re * inv, s.im * inv};
+      const double inv = 1.0 / L[i * ld + i].re;
+      xs[i * kRotMaxCols + j] = c128{s.re * inv, s.im * inv};
     }
+    c128* Ck = C_ + (long)k * m * nsel;
     for (int i = 0; i < m; ++i) {
-      const c128 x = Ck[i * nsel + j];
+      const c128 x = xs[i * kRotMaxCols + j];
       Ck[i * nsel + j] = c128{d[i] * x.re, d[i] * x.im};
     }
     lam_[(long)k * nsel + j] = ev[col];
@@ -401,7 +433,7 @@ hipError_t launch_lock(c128* a, const double* norms, double w, double tol, long 
 
 hipError_t launch_rayleigh_ritz(const c128* S, const c128* A, int m, int nsel, int nkeep, c128* C, double* lam,
                                 int* status, int nk, hipStream_t st) {
-  if (m <= 0 || m > kEigMax || nsel <= 0 || nsel > m) return hipErrorInvalidValue;
+  if (m <= 0 || m > kEigMax || nsel <= 0 || nsel > m || nsel > kRotMaxCols) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rayleigh_ritz_kernel, dim3((unsigned)nk), dim3(kEigThreads), 0, st, S, A, m, nsel, nkeep, C, lam,
                      status);
   return hipGetLastError();

@@ -30,7 +30,8 @@ hipError_t launch_resid(c128* R, const c128* HX, const c128* X, const double* la
                         hipStream_t st);
 // a[f][r] = 0 for the fields f with sqrt(w norms[f]) <= tol (norms: sum_r |residual|^2 per field)
 hipError_t launch_lock(c128* a, const double* norms, double w, double tol, long nr, long count, hipStream_t st);
-// per k: the nsel lowest solutions of A c = lam S c on an m-vector basis (m <= kEigMax);
+// per k: the nsel lowest solutions of A c = lam S c on an m-vector basis (m <= kEigMax,
+// nsel <= kRotMaxCols);
 // C [nk][m][nsel], lam [nk][nsel], status[k] = dropped basis vectors among the first nkeep
 hipError_t launch_rayleigh_ritz(const c128* S, const c128* A, int m, int nsel, int nkeep, c128* C, double* lam,
                                 int* status, int nk, hipStream_t st);
