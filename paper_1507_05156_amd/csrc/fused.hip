@@ -88,16 +88,16 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = t;
 }
 
-// Pair hooks: called by every thread at the start of each pair p = k' * nb + j
-// of a work item, before the pair's loads.
+// Pair hooks: called by every thread at the start of each pair of a work item,
+// p = (k' - first k' of the item) * nb + j, before the pair's loads.
 struct NoPairHook {
   __device__ __forceinline__ void operator()(int) {}
 };
 
-// Soft lockstep of the workgroups of one XCD (persistent launch). Before each
-// pair a workgroup counts itself in on its XCD's counter and waits until every
-// workgroup of the XCD that has an item in this round has arrived at the same
-// pair. All of them read the sources in the same (k', j) order, so the source
+// Soft lockstep of the workgroups of one XCD (persistent launch). Before every
+// kLockstepPeriod-th pair of its item a workgroup counts itself in on its XCD's
+// counter and waits until every workgroup of the XCD that has an item in this
+// round has arrived at the same pair. All of them read the sources in the same (k', j) order, so the source
 // orbitals (and, for targets of one k, the kernel values) then come from L2
 // once per XCD instead of once per workgroup. The wait is bounded: after
 // kLockstepPolls polls thread 0 stops taking part, and its peers stop at their
@@ -105,6 +105,10 @@ struct NoPairHook {
 // The state lives in LDS (thread 0 alone touches it), so it holds no registers
 // across the pair.
 constexpr int kLockstepPolls = 4096;
+// pairs between waits: pacing every pair cost more in barriers and polls than
+// it kept in L2 (C2: 2.47 s every pair, 2.30 s every 4th, 2.27 s every 8th,
+// 2.32 s every 16th, 2.56 s never)
+constexpr int kLockstepPeriod = 8;
 struct LockstepState {
   int* cnt;     // this XCD's arrival counter (zero at launch)
   int target;   // arrivals of the XCD's workgroups up to and including this pair
@@ -113,7 +117,8 @@ struct LockstepState {
 };
 struct XcdLockstep {
   LockstepState* st;  // in LDS
-  __device__ __forceinline__ void operator()(int) {
+  __device__ __forceinline__ void operator()(int pair) {
+    if (pair % kLockstepPeriod != 0) return;  // uniform: every thread passes the same pair
     if (threadIdx.x == 0 && st->live) {
       int* cnt = st->cnt;
       __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -209,7 +214,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
     const bool first_ks = (ks == ks0);
     const bool last_ks = (ks == ks1 - 1);
     for (int j = 0; j < a.nb; ++j) {
-      hook(ks * a.nb + j);
+      hook((ks - ks0) * a.nb + j);
       const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
       const rsrc_t rM = make_rsrc(a.M + ((long)ks * a.nb + j) * NR, FB64);
       c64 v[N];
