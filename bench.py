@@ -113,6 +113,22 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     t_batched = _timed(lambda: pb.apply_batched(us), 3, torch)
     t_cells = _timed(lambda: [pb.apply(us[ci], cell=ci) for ci in range(3)], 3, torch)
     outs = pb.apply_batched(us)
+    # every form of the batched launch, forced through a tuning cache
+    import tempfile
+    forms = {}
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "tune.json")
+        Plan(cells, prec="fp32", tune_cache=path).apply_batched(us)
+        data = json.load(open(path))
+        key = [k for k in data if "/batched/" in k][0]
+        tuned = dict(data[key])
+        for name, form in (("persistent_kernel", 0), ("forked_cells", 1), ("cells_in_sequence", 2)):
+            data[key].update(form=form, wg_per_cu=1)
+            json.dump(data, open(path, "w"))
+            pf = Plan(cells, prec="fp32", tune_cache=path)
+            pf.apply_batched(us)
+            forms[name + "_ms"] = _timed(lambda: pf.apply_batched(us), 3, torch) * 1e3
+            del pf
     errs = []
     for ci, c in enumerate(cells):
         p64 = Plan(c, prec="fp64")
@@ -123,7 +139,9 @@ def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
         del p64, ref
     out["batched_3cells"] = {
         "cells": "16^3/27 k/8 b + 20^3/64 k/12 b + 24^3/125 k/16 b", "pairs": pairs,
-        "persistent_graph_pairs_per_s": pairs / t_batched, "persistent_graph_ms": t_batched * 1e3,
+        "batched_graph_pairs_per_s": pairs / t_batched, "batched_graph_ms": t_batched * 1e3,
+        "default_form": "forked cells (each cell's fused kernel on its own stream, one captured graph)",
+        "forms_ms": forms, "tuner_choice": tuned,
         "per_cell_launches_pairs_per_s": pairs / t_cells, "per_cell_launches_ms": t_cells * 1e3,
         "max_rel_err_per_k_vs_fp64": max(errs), "rel_err_per_cell": errs}
     del pb, us, outs

@@ -218,11 +218,14 @@ fock_status fock_eigensolve(fockmi_plan plan, int cell, const void* u_occ, const
 fock_status fock_excited_density(fockmi_plan plan, int cell, const void* phi, const void* psi, double* nex_host,
                                  void* stream);
 
-/* All cells of the plan in one persistent launch (FOCK_FP32_COMP plans with up
- * to 8 cells of grid lengths 16, 20, 24, none down-sampled), replayed from a
+/* All cells of the plan in one launch (FOCK_FP32_COMP plans with up to 8
+ * cells of grid lengths 16, 20, 24, none down-sampled), replayed from a
  * captured hipGraph while the same buffers are passed: u_occ[c], phi[c],
  * vphi[c] as in fock_apply for cell c, nphi[c] targets. Host arrays of device
- * pointers, one entry per cell. Other plans run their cells one after another.
+ * pointers, one entry per cell. The graph holds either one persistent kernel
+ * over all cells or each cell's fused kernel on a stream of its own, forked
+ * from the caller's stream (the default); a plan with a tuning cache measures
+ * both on its first call. Other plans run their cells one after another.
  * Stream-ordered. */
 fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
                                const int* nphi, void* const* vphi, void* stream);

@@ -1,5 +1,8 @@
-// fock_apply_batched: all cells of a plan in one persistent launch, replayed
-// from a captured hipGraph while the caller passes the same buffers.
+// fock_apply_batched: all cells of a plan in one launch, replayed from a
+// captured hipGraph while the caller passes the same buffers. Three forms: one
+// persistent kernel over all cells (0), each cell's own fused kernel on a
+// forked stream (1), or those kernels one after another (2); the tuner
+// measures all three.
 //
 // Per call: one complex64 shadow per orbital array (and per distinct target
 // array), a reset of the sub-queue counters (a one-thread kernel, no memset
@@ -42,6 +45,14 @@ void BatchState::release() {
   counters.release();
   if (cap) (void)hipStreamDestroy(cap);
   cap = nullptr;
+  for (int i = 0; i < kMaxBatchCells; ++i) {
+    if (side[i]) (void)hipStreamDestroy(side[i]);
+    if (join[i]) (void)hipEventDestroy(join[i]);
+    side[i] = nullptr;
+    join[i] = nullptr;
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  fork = nullptr;
   key.clear();
 }
 
@@ -55,6 +66,29 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
                               hipStream_t st) {
   const int nc = (int)cells.size();
   BatchState& B = bstate;
+  // the cells in decreasing cost
+  std::vector<int> by_cost(nc);
+  std::iota(by_cost.begin(), by_cost.end(), 0);
+  std::stable_sort(by_cost.begin(), by_cost.end(),
+                   [&](int x, int y) { return item_cost(cells[x]) * cells[x].nk > item_cost(cells[y]) * cells[y].nk; });
+  // form 1: every cell's fused kernel (its grid form, one workgroup per target)
+  // on its own stream, so that the cells' last rounds may overlap; form 2: the
+  // same kernels one after another on the caller's stream, costliest first
+  auto launch_cells = [&](hipStream_t q, bool forked) -> fock_status {
+    hipError_t ee;
+    if (forked && (ee = hipEventRecord(B.fork, q)) != hipSuccess) return hip_fail(ee, "fork");
+    for (int ci : by_cost) {
+      FusedArgs a = B.args.cells[ci];
+      a.xcd_map = 1;
+      hipStream_t cs = forked ? B.side[ci] : q;
+      if (forked && (ee = hipStreamWaitEvent(cs, B.fork, 0)) != hipSuccess) return hip_fail(ee, "fork");
+      if ((ee = launch_fused_apply(a.n, a, cs, 0)) != hipSuccess) return hip_fail(ee, "cell kernel");
+      if (forked && (ee = hipEventRecord(B.join[ci], cs)) != hipSuccess) return hip_fail(ee, "join");
+    }
+    for (int ci = 0; forked && ci < nc; ++ci)
+      if ((ee = hipStreamWaitEvent(q, B.join[ci], 0)) != hipSuccess) return hip_fail(ee, "join");
+    return FOCK_OK;
+  };
   std::vector<const void*> key;
   for (int ci = 0; ci < nc; ++ci) {
     key.push_back(u[ci]);
@@ -113,8 +147,12 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
     bool measure = false;
     {
       TuneEntry te;
-      if (tune.get(tkey, &te)) mult = std::max(1, (int)te.fields["wg_per_cu"]);
-      else measure = tuning;
+      if (tune.get(tkey, &te)) {
+        mult = std::max(1, (int)te.fields["wg_per_cu"]);
+        B.form = te.fields.count("form") ? (int)te.fields["form"] : kDefaultBatchForm;
+      } else {
+        measure = tuning;
+      }
     }
     B.nwg = num_cus * mult;
     for (int ci = 0; ci < nc; ++ci) {
@@ -165,6 +203,15 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
     }
     if (!B.cap && (e = hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "capture stream");
+    // streams (default priority) and events of the forked form
+    if (!B.fork && (e = hipEventCreateWithFlags(&B.fork, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "fork event");
+    for (int ci = 0; ci < nc; ++ci) {
+      if (!B.side[ci] && (e = hipStreamCreateWithFlags(&B.side[ci], hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "cell stream");
+      if (!B.join[ci] && (e = hipEventCreateWithFlags(&B.join[ci], hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "join event");
+    }
     B.ready = true;
     if (measure) {
       // persistent workgroups per CU: each candidate runs the whole batch on
@@ -182,24 +229,33 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
       if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tuning event");
       if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
       double best = 1e300;
-      int bm = 1;
-      for (int m : {1, 2}) {
+      int bm = 1, bf = 0;
+      // persistent with 1 or 2 workgroups per CU (m = 1, 2), the forked cells (m = 0),
+      // the cells in sequence (m = -1)
+      for (int m : {1, 2, 0, -1}) {
         (void)hipEventRecord(e0, st);
-        if ((e = launch_fused_batched(B.args, B.nthreads, num_cus * m, st)) != hipSuccess)
-          return hip_fail(e, "persistent kernel");
+        if (m > 0) {
+          if ((e = launch_fused_batched(B.args, B.nthreads, num_cus * m, st)) != hipSuccess)
+            return hip_fail(e, "persistent kernel");
+        } else if ((s = launch_cells(st, m == 0)) != FOCK_OK) {
+          return s;
+        }
         (void)hipEventRecord(e1, st);
         if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
           best = ms;
-          bm = m;
+          bm = m > 0 ? m : bm;
+          bf = m > 0 ? 0 : (m == 0 ? 1 : 2);
         }
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
+      B.form = bf;
       TuneEntry te;
       te.fields["wg_per_cu"] = bm;
+      te.fields["form"] = bf;
       te.fields["ms"] = best;
       tune.put(tkey, te);
       save_tune();
@@ -218,6 +274,7 @@ fock_status Plan::run_batched(const void* const* u, const void* const* phi, cons
           (ee = launch_to_c64((c64*)B.shadow_x[ci].ptr, (const c128*)phi[ci], nx, q)) != hipSuccess)
         return hip_fail(ee, "batched shadow");
     }
+    if (B.form == 1 || B.form == 2) return launch_cells(q, B.form == 1);
     if ((ee = launch_fused_batched(B.args, B.nthreads, B.nwg, q)) != hipSuccess)
       return hip_fail(ee, "persistent kernel");
     return FOCK_OK;

@@ -63,6 +63,11 @@ struct Cell {
   PairSet rev() const { return {nsrc, nk, (const int*)(ds ? qidx_st.ptr : qidx.ptr)}; }
 };
 
+// the batched form used when no tuned choice exists: the forked cells (three
+// cells 16^3/27 k/8 b, 20^3/64 k/12 b, 24^3/125 k/16 b: 257.5 ms, against 261.8
+// in sequence and 282.2 for the persistent kernel)
+constexpr int kDefaultBatchForm = 1;
+
 // state of the batched persistent launch (fock_apply_batched): buffers whose
 // addresses a captured graph refers to, and the graph itself
 struct BatchState {
@@ -74,6 +79,12 @@ struct BatchState {
   hipStream_t cap = nullptr;
   BatchArgs args{};
   int nthreads = 0, nwg = 0, entries = 0;
+  // form 0: the persistent kernel; form 1: each cell's own fused kernel on a
+  // stream of its own, forked from and joined to the caller's stream; form 2:
+  // those kernels one after another, costliest cell first
+  int form = kDefaultBatchForm;
+  hipStream_t side[kMaxBatchCells] = {};
+  hipEvent_t fork = nullptr, join[kMaxBatchCells] = {};
   bool ready = false;
   void reset_graph();
   void release();

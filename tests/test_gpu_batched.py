@@ -139,3 +139,40 @@ def test_batched_autotuner_writes_and_reuses_cache(device, tmp_path):
     for o, o2, r in zip(outs, outs2, ref):
         assert rel(o.cpu().numpy(), r.cpu().numpy()) < 1e-6
         assert rel(o2.cpu().numpy(), r.cpu().numpy()) < 1e-6
+
+
+def test_batched_forms_agree(device, tmp_path):
+    """The three forms of the batched launch, forced through the tuning cache: the persistent
+    kernel over all cells (form 0) and each cell's own kernel on a forked stream
+    (form 1) or in sequence (form 2). Each replays its captured graph bit for bit;
+    forms 1 and 2 agree bit for bit; forms 0 and 1 run the same
+    per-target steps compiled into different kernels (FP32 contraction may differ),
+    so they agree to FP32 rounding and both match the FP64 path."""
+    print("[gpu] batched forms", flush=True)
+    from paper_1507_05156_amd.api import Plan
+    path = str(tmp_path / "tune.json")
+    cs = cells_small()
+    descs = [{k: v for k, v in c.items() if k != "u"} for c in cs]
+    us = [to_dev(c["u"]) for c in cs]
+    Plan(descs, prec="fp32", tune_cache=path).apply_batched(us)   # writes the batched entry
+    data = json.load(open(path))
+    key = [k for k in data if "/batched/" in k][0]
+    assert data[key]["form"] in (0, 1, 2)
+    outs = {}
+    for form in (0, 1, 2):
+        data[key]["form"] = form
+        data[key]["wg_per_cu"] = 1
+        json.dump(data, open(path, "w"))
+        plan = Plan(descs, prec="fp32", tune_cache=path)
+        first = [o.cpu().numpy() for o in plan.apply_batched(us)]
+        again = [o.cpu().numpy() for o in plan.apply_batched(us)]   # graph replay
+        for a, b in zip(first, again):
+            assert np.array_equal(a, b)
+        outs[form] = first
+    for a, b, c in zip(outs[0], outs[1], outs[2]):
+        assert rel(a, b) < 1e-6
+        assert np.array_equal(b, c)   # forms 1 and 2 run the same kernels
+    ref = [Plan(d, prec="fp64").apply(u).cpu().numpy() for d, u in zip(descs, us)]
+    for form in (0, 1, 2):
+        for o, r in zip(outs[form], ref):
+            assert rel(o, r) < 1e-6, form
