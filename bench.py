@@ -65,20 +65,53 @@ def flops_per_pair(nr: int) -> float:
     return 10.0 * nr * math.log2(nr) + 16.0 * nr
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(u, kp, cell, omega, nsrc):
-    """The FP64 oracle on one output row against the first nsrc source k-points."""
+    """The FP64 oracle on one output row against the first nsrc source k-points.
+    Returns pairs/s, wall seconds, pairs, the threads it kept busy on average
+    (process CPU time over wall time) and the size of the BLAS thread pool."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
-        threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        pool = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        pool = os.cpu_count() or 1
     us = u[:nsrc]
+    c0 = time.process_time()
     t0 = time.perf_counter()
     oracle.fock_apply(us, us, kp[:nsrc], cell, omega, rows=[(0, 0)])
     dt = time.perf_counter() - t0
+    busy = (time.process_time() - c0) / dt
     pairs = nsrc * u.shape[1]
-    return pairs / dt, dt, pairs, threads
+    return pairs / dt, dt, pairs, max(1, round(busy)), pool
+
+
+def copy_bandwidth(torch, dev, mib=1024, reps=5):
+    """Best device-to-device copy rate (bytes read + written per second, GB/s)
+    of a mib-MiB buffer: the HBM rate a plain copy kernel reaches."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    return 2.0 * (mib << 20) / best / 1e9
 
 
 def _timed(fn, reps, torch):
@@ -302,7 +335,7 @@ def main():
                     help="FP64 comparison path: the plain staged path (the reference of the speed-up), or the "
                          "fused FP64 form (cubic 16^3-24^3 grids)")
     ap.add_argument("--cpu-sources", type=int, default=96, help="source k-points in the oracle sample (0 = skip)")
-    ap.add_argument("--extras", type=int, default=1, help="1: also time the batched launch, adjoint, Taylor step, "
+    ap.add_argument("--extras", type=int, default=1, help="1: also time the batched launch, adjoint, Taylor step, a device copy, "
                     "energy and orthonormalisation")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size kernel for HBM counter scaling)")
@@ -398,16 +431,19 @@ def main():
         del plan64, out64
 
     extras = extra_legs(torch, np, synth, Plan, omega, dev, ud, plan32) if args.extras else None
+    copy_gbs = copy_bandwidth(torch, dev) if args.extras else None
 
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if args.cpu_sources > 0:
         nsrc = min(args.cpu_sources, nk)
-        pps, dt, cpairs, threads = cpu_baseline(u, kp, cell, omega, nsrc)
+        pps, dt, cpairs, threads, pool = cpu_baseline(u, kp, cell, omega, nsrc)
         cpu = {"value": pps, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                "sample": f"output row (k=0, i=0) against {nsrc} source k-points x {nb} bands = {cpairs} pairs "
-                         f"of the {n}^3 workload, {dt:.1f} s"}
-        print(f"[bench] cpu oracle: {pps:.1f} pairs/s on {threads} threads", file=sys.stderr, flush=True)
+                         f"of the {n}^3 workload, {dt:.1f} s",
+               "blas_pool_threads": pool, "host": host_cpu_model()}
+        print(f"[bench] cpu oracle: {pps:.1f} pairs/s, {threads} threads busy of a pool of {pool}",
+              file=sys.stderr, flush=True)
 
     rec = {
         "metric": "Fock pair-FFTs/s: FP64 plain vs FP32 batched at \u22641e-6 rel err; % HBM peak",
@@ -436,7 +472,9 @@ def main():
                      "valu_frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS,
                      "valu_peak_unpacked_TFLOPs": FP32_VALU_PEAK_TFLOPS / 2,
                      "valu_frac_unpacked": achieved_tflops / (FP32_VALU_PEAK_TFLOPS / 2),
-                     "flops_per_pair": flops_per_pair(nr)},
+                     "flops_per_pair": flops_per_pair(nr),
+                     "copy_GBs_measured": copy_gbs,
+                     "frac_of_measured_copy": achieved_gbs / copy_gbs if copy_gbs else None},
         "ffts_per_s": 2 * value,
         "fp32_repeat_bitwise_equal": repeat_equal,
         "cpu_baseline": cpu,

@@ -1,4 +1,5 @@
 // In-register mixed-radix FFTs for one thread (lengths built from 2, 3, 4, 5).
+// Lengths with an odd factor use the prime-factor mapping at the top level.
 //
 // Every loop below runs over compile-time indices (static_for), so after
 // inlining each array element is a named register and every twiddle factor is
@@ -9,7 +10,15 @@
 // Input and output are both in natural order.
 #pragma once
 
+// FOCKMI_FFT_HOST_CHECK builds only the arithmetic (complex type, twiddles,
+// transforms) as plain host C++, for the CPU test that compares the
+// transforms with a direct DFT; the build of the library never defines it.
+#ifdef FOCKMI_FFT_HOST_CHECK
+#define __device__
+#define __forceinline__ inline
+#else
 #include <hip/hip_runtime.h>
+#endif
 
 #include <type_traits>
 #include <utility>
@@ -45,6 +54,7 @@ __device__ __forceinline__ cx<T> mul_si(cx<T> a) {
   else return {a.im, -a.re};
 }
 
+#ifndef FOCKMI_FFT_HOST_CHECK
 // ------------------------------------------------------------ buffer access
 // Raw buffer loads/stores: a uniform 128-bit resource (base pointer, size in
 // bytes) plus one per-thread byte offset and a uniform byte offset. Every load
@@ -76,6 +86,8 @@ __device__ __forceinline__ void st_c128(cx<double> v, rsrc_t r, unsigned voff, u
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v.re), r, voff, soff, 0);
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v.im), r, voff + 8u, soff, 0);
 }
+
+#endif  // FOCKMI_FFT_HOST_CHECK
 
 // ---------------------------------------------------------------- static_for
 template <typename F, int... I>
@@ -163,6 +175,42 @@ __device__ __forceinline__ cx<T> twiddle(cx<T> x) {
   }
 }
 
+// A twiddled value x * w, w = exp(SIGN * 2 pi i E / N), as m * u: m is a
+// compile-time real factor (the larger of |Re w|, |Im w|, with its sign; 1
+// for the trivial angles) and u = x * (w / m) costs at most two fused
+// multiply-adds, since one component of w / m is exactly 1. The butterflies
+// below fold m into their own multiply-adds (after Linzer and Feig's
+// FMA-oriented radix-2 and radix-4 FFTs), so a twiddle costs two
+// instructions instead of four.
+template <int N, int SIGN, int E>
+struct tw_split {
+  static constexpr int e = ((E % N) + N) % N;
+  static constexpr bool trivial = (4 * e) % N == 0;
+  static constexpr bool eighth = !trivial && (8 * e) % N == 0;
+  static constexpr ct::CS w = ct::cis(e, N);
+  static constexpr double c = w.c;
+  static constexpr double s = SIGN > 0 ? w.s : -w.s;
+  static constexpr bool cos_major = (c < 0 ? -c : c) >= (s < 0 ? -s : s);
+  static constexpr double m = trivial ? 1.0 : (cos_major ? c : s);
+};
+template <int N, int SIGN, int E, typename T>
+__device__ __forceinline__ cx<T> tw_unit(cx<T> x) {
+  using S = tw_split<N, SIGN, E>;
+  if constexpr (S::trivial) {
+    return twiddle<N, SIGN, E>(x);
+  } else if constexpr (S::eighth) {
+    // w / m = 1 + i sigma with sigma = +-1 exactly
+    if constexpr ((S::c > 0) == (S::s > 0)) return {x.re - x.im, x.im + x.re};
+    else return {x.re + x.im, x.im - x.re};
+  } else if constexpr (S::cos_major) {
+    constexpr T t = (T)(S::s / S::c);  // w / m = 1 + i t
+    return {x.re - t * x.im, x.im + t * x.re};
+  } else {
+    constexpr T t = (T)(S::c / S::s);  // w / m = t + i
+    return {t * x.re - x.im, t * x.im + x.re};
+  }
+}
+
 // --------------------------------------------------------------- base DFTs
 template <int R, int SIGN, typename T>
 __device__ __forceinline__ void dft_base(cx<T> (&x)[R]) {
@@ -209,6 +257,23 @@ __device__ __forceinline__ void dft_base(cx<T> (&x)[R]) {
   }
 }
 
+// N = A * B with A the largest power of two dividing N: when both parts
+// exceed 1 they are coprime, and the prime-factor (Good-Thomas) mapping
+// applies: n = (B n1 + A n2) mod N on input, k = CRT(k mod A, k mod B) on
+// output, with no twiddle factors between the A- and B-point transforms.
+template <int N>
+constexpr int pow2_part() {
+  int a = 1;
+  while ((N / a) % 2 == 0) a *= 2;
+  return a;
+}
+template <int A, int B>
+constexpr int crt_index(int k1, int k2) {
+  for (int k = 0; k < A * B; ++k)
+    if (k % A == k1 && k % B == k2) return k;
+  return -1;
+}
+
 template <int N>
 constexpr int first_radix() {
   if constexpr (N % 4 == 0) return 4;
@@ -217,14 +282,45 @@ constexpr int first_radix() {
   else return 5;
 }
 
+// Whether a transform of length N folds its twiddle factors into the radix-2
+// and radix-4 butterflies (tw_split). The 32-point transform keeps plain
+// twiddle multiplies throughout: the 32^3 pair kernel has fewer instructions
+// with folding but ran slower in its paced persistent form.
+template <int N>
+constexpr bool fold_default() { return N != 32; }
+
 // Decimation in time: N = R * M. The M-point transforms of the R
 // subsequences x[R m + r] are combined by R-point transforms after twiddling.
-template <int N, int SIGN, typename T>
+template <int N, int SIGN, bool FOLD = fold_default<N>(), typename T>
 __device__ __forceinline__ void fft(cx<T> (&x)[N]) {
   if constexpr (N == 1) {
     return;
   } else if constexpr (N == 2 || N == 3 || N == 4 || N == 5) {
     dft_base<N, SIGN>(x);
+  } else if constexpr (pow2_part<N>() > 1 && pow2_part<N>() < N) {
+    // prime-factor algorithm: B-point transforms of the A interleaved
+    // subsequences, then A-point transforms across them
+    constexpr int A = pow2_part<N>();
+    constexpr int B = N / A;
+    cx<T> z[A][B];
+    static_for<A>([&](auto n1) {
+      constexpr int a1 = decltype(n1)::value;
+      static_for<B>([&](auto n2) {
+        constexpr int b2 = decltype(n2)::value;
+        z[a1][b2] = x[(a1 * B + b2 * A) % N];
+      });
+      fft<B, SIGN, FOLD>(z[a1]);
+    });
+    static_for<B>([&](auto k2) {
+      constexpr int kb = decltype(k2)::value;
+      cx<T> w[A];
+      static_for<A>([&](auto n1) { w[decltype(n1)::value] = z[decltype(n1)::value][kb]; });
+      fft<A, SIGN, FOLD>(w);
+      static_for<A>([&](auto k1) {
+        constexpr int ka = decltype(k1)::value;
+        x[crt_index<A, B>(ka, kb)] = w[ka];
+      });
+    });
   } else {
     constexpr int R = first_radix<N>();
     constexpr int M = N / R;
@@ -236,20 +332,46 @@ __device__ __forceinline__ void fft(cx<T> (&x)[N]) {
         constexpr int mm = decltype(m)::value;
         y[rr][mm] = x[mm * R + rr];
       });
-      fft<M, SIGN>(y[rr]);
+      fft<M, SIGN, FOLD>(y[rr]);
     });
     static_for<M>([&](auto k1) {
       constexpr int kk = decltype(k1)::value;
-      cx<T> z[R];
-      static_for<R>([&](auto r) {
-        constexpr int rr = decltype(r)::value;
-        z[rr] = twiddle<N, SIGN, rr * kk>(y[rr][kk]);
-      });
-      dft_base<R, SIGN>(z);
-      static_for<R>([&](auto k2) {
-        constexpr int k2v = decltype(k2)::value;
-        x[kk + M * k2v] = z[k2v];
-      });
+      if constexpr (R == 2 && FOLD) {
+        constexpr T m1 = (T)tw_split<N, SIGN, kk>::m;
+        const cx<T> y0 = y[0][kk];
+        const cx<T> u1 = tw_unit<N, SIGN, kk>(y[1][kk]);
+        x[kk] = {y0.re + m1 * u1.re, y0.im + m1 * u1.im};
+        x[kk + M] = {y0.re - m1 * u1.re, y0.im - m1 * u1.im};
+      } else if constexpr (R == 4 && FOLD) {
+        // z_r = m_r u_r; z1 + z3 and z1 - z3 are m1 (u1 +- (m3/m1) u3)
+        constexpr double m1d = tw_split<N, SIGN, kk>::m;
+        constexpr T m1 = (T)m1d;
+        constexpr T m2 = (T)tw_split<N, SIGN, 2 * kk>::m;
+        constexpr T rho = (T)(tw_split<N, SIGN, 3 * kk>::m / m1d);
+        const cx<T> y0 = y[0][kk];
+        const cx<T> u1 = tw_unit<N, SIGN, kk>(y[1][kk]);
+        const cx<T> u2 = tw_unit<N, SIGN, 2 * kk>(y[2][kk]);
+        const cx<T> u3 = tw_unit<N, SIGN, 3 * kk>(y[3][kk]);
+        const cx<T> a = {y0.re + m2 * u2.re, y0.im + m2 * u2.im};
+        const cx<T> b = {y0.re - m2 * u2.re, y0.im - m2 * u2.im};
+        const cx<T> c = {u1.re + rho * u3.re, u1.im + rho * u3.im};
+        const cx<T> d = mul_si<SIGN>(cx<T>{u1.re - rho * u3.re, u1.im - rho * u3.im});
+        x[kk] = {a.re + m1 * c.re, a.im + m1 * c.im};
+        x[kk + 2 * M] = {a.re - m1 * c.re, a.im - m1 * c.im};
+        x[kk + M] = {b.re + m1 * d.re, b.im + m1 * d.im};
+        x[kk + 3 * M] = {b.re - m1 * d.re, b.im - m1 * d.im};
+      } else {
+        cx<T> z[R];
+        static_for<R>([&](auto r) {
+          constexpr int rr = decltype(r)::value;
+          z[rr] = twiddle<N, SIGN, rr * kk>(y[rr][kk]);
+        });
+        dft_base<R, SIGN>(z);
+        static_for<R>([&](auto k2) {
+          constexpr int k2v = decltype(k2)::value;
+          x[kk + M * k2v] = z[k2v];
+        });
+      }
     });
   }
 }
