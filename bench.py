@@ -32,10 +32,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
 # the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "d8eebc9a7ecb0c7fb78b1adfd2d55ad6d771d0e2b962ff4c979c0704960d02c3",
+    "sources_sha256": "5cbbb70762823c2f92e1ec2bd4f99596520415e4d75029c10d21f13414c13631",
     "workload": 2,
-    "fetch_kib": 3689882718.8125, "write_kib": 3822685356.3125,
-    "fetch_scale": 1.999883181719894, "write_scale": 1.0,
+    "fetch_kib": 3690246602.5, "write_kib": 3822687750.25,
+    "fetch_scale": 1.9998860424127254, "write_scale": 1.0,
 }
 KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/fft_reg.hpp",
                   "paper_1507_05156_amd/csrc/fused_common.hpp", "paper_1507_05156_amd/csrc/kernels.hpp")

@@ -47,6 +47,14 @@ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + a * b with each product term fused into the accumulator: two
+// multiply-adds per component, against three for acc + cmul(a, b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b) {
+  return {fmadd(-a.im, b.im, fmadd(a.re, b.re, acc.re)), fmadd(a.im, b.re, fmadd(a.re, b.im, acc.im))};
+}
 // multiply by s * i with s = +-1
 template <int S, typename T>
 __device__ __forceinline__ cx<T> mul_si(cx<T> a) {

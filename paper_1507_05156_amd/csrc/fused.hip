@@ -213,6 +213,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
     const rsrc_t rK = make_rsrc(a.Kt + (long)qi * NR, NR * 4u);
     const bool first_ks = (ks == ks0);
     const bool last_ks = (ks == ks1 - 1);
+    if constexpr (ACCREG) static_for<N>([&](auto m) { acc[decltype(m)::value] = c64{0.0f, 0.0f}; });
     for (int j = 0; j < a.nb; ++j) {
       hook((ks - ks0) * a.nb + j);
       const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
@@ -317,8 +318,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
           __builtin_amdgcn_sched_barrier(0);
           static_for<G>([&](auto q) {
             constexpr int m1 = C0 + decltype(q)::value;
-            const c64 prod = cmul(mv[q], v[m1]);
-            acc[m1] = (j == 0) ? prod : acc[m1] + prod;
+            acc[m1] = cmac(acc[m1], mv[q], v[m1]);
             v[m1] = acc[m1];
           });
         });

@@ -219,7 +219,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
           __builtin_amdgcn_sched_barrier(0);
           static_for<G>([&](auto q) {
             constexpr int m1 = C0 + decltype(q)::value;
-            acc[m1] = acc[m1] + cmul(mv[q], v[m1]);
+            acc[m1] = cmac(acc[m1], mv[q], v[m1]);
           });
         });
       } else {
