@@ -575,7 +575,7 @@ int fused_variants(int n) { return (n == 16 || n == 20 || n == 32) ? 2 : 1; }
 bool fused_has_lockstep(int n) { return n == 32; }
 
 // without a tuned choice: the lockstep form where it exists (measured faster at
-// 32^3: 2.52 s against 2.61 s per application of 11,943,936 pairs)
+// 32^3: 2.27 s against 2.63 s per application of 11,943,936 pairs)
 int fused_default_variant(int n) { return n == 32 ? 1 : 0; }
 
 hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant, const LockstepCfg* ls) {
