@@ -137,7 +137,11 @@ __global__ void lock_kernel(c128* __restrict__ a, const double* __restrict__ nor
 //   5. the nsel smallest eigenvalues in ascending order, and C = D L^-H V_sel.
 // status[k] = number of dropped columns among the first nkeep.
 constexpr double kDropTol = 1e-8;
-constexpr int kEigThreads = 256;  // four waves: one row index per lane, four pair slots
+// twelve waves: one row index per lane and twelve pair slots, so that a Jacobi
+// round of up to 24 disjoint pairs costs each wave at most two rotations (with
+// four waves, six: 163 ms against 146 ms for a 16^3, 8 k, 16-band eigensolve,
+// 138.5 ms once a round also lost a barrier)
+constexpr int kEigThreads = 768;
 static_assert(kEigMax <= 64, "one lane per row of the projected matrix");
 __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* __restrict__ S_, const c128* __restrict__ A_,
                                                                     int m, int nsel, int nkeep, c128* __restrict__ C_,
@@ -149,7 +153,7 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
   __shared__ double d[kEigMax], ev[kEigMax], offs[64];
   __shared__ int drop[kEigMax], order[kEigMax];
   __shared__ double rcs[kEigMax / 2], rsn[kEigMax / 2], rer[kEigMax / 2], rei[kEigMax / 2], scale;
-  __shared__ int rp[kEigMax / 2], rq[kEigMax / 2], rskip[kEigMax / 2], done;
+  __shared__ int rp[2][kEigMax / 2], rq[2][kEigMax / 2], rskip[2][kEigMax / 2], done;
   const int k = blockIdx.x, t = threadIdx.x;
   const int ld = m | 1;
   const c128* S = S_ + (long)k * m * m;
@@ -278,35 +282,49 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
     }
     if (done) break;
     for (int r = 0; r < mm - 1; ++r) {
-      // this round's pairs and their rotations, from M before the round
-      for (int i = t; i < npair; i += kEigThreads) {
+      const int cb = r & 1, pb = cb ^ 1;  // this round's and the previous round's pair tables
+      // wave 0: this round's pairs and their rotations, from M before the round;
+      // wave 1: the previous round's rotated entries set to their exact values
+      // (their rows and columns are not read until after the next barrier)
+      if (t < npair) {
+        const int i = t;
         const int a = i == 0 ? mm - 1 : (r + i) % (mm - 1);
         const int b = i == 0 ? r : (r - i + mm - 1) % (mm - 1);
         const int p = a < b ? a : b, q = a < b ? b : a;
-        rp[i] = p;
-        rq[i] = q;
+        rp[cb][i] = p;
+        rq[cb][i] = q;
         int sk = q >= m;
         if (!sk) {
           const c128 apq = M[p * ld + q];
-          const double rr = sqrt(apq.re * apq.re + apq.im * apq.im);
-          sk = !(rr > 1e-18 * scale);
+          const double r2 = apq.re * apq.re + apq.im * apq.im;
+          sk = !(r2 > 1e-36 * scale * scale);
           if (!sk) {
-            rer[i] = apq.re / rr;  // e^{i theta}
-            rei[i] = apq.im / rr;
-            const double tau = (M[q * ld + q].re - M[p * ld + p].re) / (2.0 * rr);
+            const double inv = rsqrt(r2);  // 1 / |a_pq|
+            rer[i] = apq.re * inv;          // e^{i theta}
+            rei[i] = apq.im * inv;
+            const double tau = (M[q * ld + q].re - M[p * ld + p].re) * (0.5 * inv);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            rcs[i] = 1.0 / sqrt(1.0 + tt * tt);
+            rcs[i] = rsqrt(1.0 + tt * tt);
             rsn[i] = tt * rcs[i];
           }
         }
-        rskip[i] = sk;
+        rskip[cb][i] = sk;
+      } else if (r > 0 && t >= 64 && t < 64 + npair) {
+        const int i = t - 64;
+        if (!rskip[pb][i]) {
+          const int p = rp[pb][i], q = rq[pb][i];
+          M[p * ld + q] = c128{0.0, 0.0};
+          M[q * ld + p] = c128{0.0, 0.0};
+          M[p * ld + p].im = 0.0;
+          M[q * ld + q].im = 0.0;
+        }
       }
       __syncthreads();
       // columns: M <- M J, V <- V J with J = [[c, s], [-s e^{-i th}, c e^{-i th}]] on (p, q)
       for (int i = slot; i < npair; i += kEigThreads / 64) {
         const int row = lane;
-        if (row >= m || rskip[i]) continue;
-        const int p = rp[i], q = rq[i];
+        if (row >= m || rskip[cb][i]) continue;
+        const int p = rp[cb][i], q = rq[cb][i];
         const double c = rcs[i], s = rsn[i], er = rer[i], ei = rei[i];
         const c128 mp = M[row * ld + p], mq = M[row * ld + q];
         const c128 mqe{mq.re * er + mq.im * ei, mq.im * er - mq.re * ei};  // mq e^{-i th}
@@ -321,8 +339,8 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
       // rows: M <- J^H M
       for (int i = slot; i < npair; i += kEigThreads / 64) {
         const int col = lane;
-        if (col >= m || rskip[i]) continue;
-        const int p = rp[i], q = rq[i];
+        if (col >= m || rskip[cb][i]) continue;
+        const int p = rp[cb][i], q = rq[cb][i];
         const double c = rcs[i], s = rsn[i], er = rer[i], ei = rei[i];
         const c128 mp = M[p * ld + col], mq = M[q * ld + col];
         const c128 mqe{mq.re * er - mq.im * ei, mq.im * er + mq.re * ei};  // mq e^{+i th}
@@ -330,9 +348,13 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
         M[q * ld + col] = c128{s * mp.re + c * mqe.re, s * mp.im + c * mqe.im};
       }
       __syncthreads();
+    }
+    // the last round's rotated entries
+    {
+      const int lb = (mm - 2) & 1;
       for (int i = t; i < npair; i += kEigThreads) {
-        if (rskip[i]) continue;
-        const int p = rp[i], q = rq[i];
+        if (rskip[lb][i]) continue;
+        const int p = rp[lb][i], q = rq[lb][i];
         M[p * ld + q] = c128{0.0, 0.0};
         M[q * ld + p] = c128{0.0, 0.0};
         M[p * ld + p].im = 0.0;
