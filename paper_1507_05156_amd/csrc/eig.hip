@@ -154,6 +154,7 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
   __shared__ int drop[kEigMax], order[kEigMax];
   __shared__ double rcs[kEigMax / 2], rsn[kEigMax / 2], rer[kEigMax / 2], rei[kEigMax / 2], scale;
   __shared__ int rp[2][kEigMax / 2], rq[2][kEigMax / 2], rskip[2][kEigMax / 2], done;
+  __shared__ int cidx[kEigMax], mc;  // the directions that were not dropped, ascending
   const int k = blockIdx.x, t = threadIdx.x;
   const int ld = m | 1;
   const c128* S = S_ + (long)k * m * m;
@@ -259,11 +260,21 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
   }
   __syncthreads();
 
-  // parallel cyclic Jacobi: every round rotates mm/2 disjoint pairs at once (the
-  // circle method over mm = m rounded up to even; pairs with the padding index
-  // are skipped). Rotations on disjoint pairs commute, so a round equals its
-  // rotations applied one after another; a sweep of mm - 1 rounds meets every pair.
-  const int mm = m + (m & 1), npair = mm / 2;
+  // parallel cyclic Jacobi over the directions that were not dropped (the
+  // dropped ones are already decoupled): every round rotates mm/2 disjoint pairs
+  // at once (the circle method over mm = mc rounded up to even; pairs with the
+  // padding index are skipped). Rotations on disjoint pairs commute, so a round
+  // equals its rotations applied one after another; a sweep of mm - 1 rounds
+  // meets every pair. Locked bands drop their W and P columns, so late
+  // iterations rotate fewer pairs.
+  if (t == 0) {
+    int n = 0;
+    for (int i = 0; i < m; ++i)
+      if (!drop[i]) cidx[n++] = i;
+    mc = n;
+  }
+  __syncthreads();
+  const int mm = mc + (mc & 1), npair = mm / 2;
   const int lane = t & 63, slot = t >> 6;  // row (or column) index, pair slot
   for (int sweep = 0; sweep < 40; ++sweep) {
     // largest off-diagonal modulus: per-lane maxima over rows, then one lane
@@ -290,10 +301,11 @@ __global__ void __launch_bounds__(kEigThreads) rayleigh_ritz_kernel(const c128* 
         const int i = t;
         const int a = i == 0 ? mm - 1 : (r + i) % (mm - 1);
         const int b = i == 0 ? r : (r - i + mm - 1) % (mm - 1);
-        const int p = a < b ? a : b, q = a < b ? b : a;
+        const int lo = a < b ? a : b, hi = a < b ? b : a;  // compact indices
+        int sk = hi >= mc;
+        const int p = sk ? 0 : cidx[lo], q = sk ? 0 : cidx[hi];
         rp[cb][i] = p;
         rq[cb][i] = q;
-        int sk = q >= m;
         if (!sk) {
           const c128 apq = M[p * ld + q];
           const double r2 = apq.re * apq.re + apq.im * apq.im;
