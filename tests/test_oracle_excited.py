@@ -94,3 +94,26 @@ def test_density_is_a_k_average(nkm):
     b = excited.excited_density(np.concatenate([phi, phi]), np.concatenate([psi, psi]), CELL)
     assert abs(a - b) < 1e-14 * abs(a)
     assert 0.0 < a < 2.0 * 2 / VOL
+
+
+def test_golden_fixture_is_the_oracle_output():
+    """tests/golden/excited_16cube.json holds what its committed script computes from the
+    oracle and the seeded inputs (dense eigh of two 4096 x 4096 Hamiltonians, about 1.5 min).
+    A change to the oracle, the inputs or the fixture that breaks this agreement fails here."""
+    import importlib.util
+    import json
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("make_excited", os.path.join(here, "golden", "make_excited_16cube.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    with open(os.path.join(here, "golden", "excited_16cube.json")) as f:
+        g = json.load(f)
+    assert g["case"] == json.loads(json.dumps(mk.CASE))
+    cell, kp, psi, v = mk.inputs()
+    eps, phi = excited.eigenstates_dense(psi, kp, cell, mk.CASE["omega"], np.array(mk.CASE["a_over_c"]),
+                                         mk.CASE["alpha"], mk.CASE["nb"], vloc=v, extra=1)
+    nb = mk.CASE["nb"]
+    assert np.max(np.abs(eps - np.array(g["eigenvalues"]))) < 1e-12
+    nex = excited.excited_density(phi[:, :nb], psi, cell)
+    assert abs(nex - g["n_ex"]) < 1e-12 * abs(g["n_ex"])
