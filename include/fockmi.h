@@ -120,6 +120,18 @@ fock_status fock_apply_krange(fockmi_plan plan, int cell, const void* u_occ, int
 fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* ex_re, double* ex_im,
                         void* stream);
 
+/* Reverse mode of fock_energy (derived from Eqs. (15)-(16) and the E_x piece of
+ * Eq. (22)): for the cotangent g_e of E_x,
+ *   g_u[k][j] <- g_e dE_x/du_{jk}   (PyTorch convention: dL/dRe + i dL/dIm)
+ * With every k-point a source this is 4 w g_e (V_x[u] u)_{jk}, w = (g_s/2)(1/N_k)(Omega/N_r).
+ * For a down-sampled cell it is 2 w g_e (V_x[u] u)_{jk} (u as the target) plus, at
+ * the source k-points k' in S, the source-side adjoint
+ *   -(2 w g_e/|S|) sum_{k,i} u_ik * W_{k'-k}(conj(u_ik) u_jk').
+ *   u_occ : device [nk][nb][N_r] complex128;  g_u : device, same shape, overwritten,
+ *           must not overlap u_occ.
+ * Stream-ordered. FOCK_ERR_ARG for NULL/misaligned pointers or a non-finite g_e. */
+fock_status fock_energy_vjp(fockmi_plan plan, int cell, const void* u_occ, double g_e, void* g_u_occ, void* stream);
+
 /* Reverse mode of fock_apply (derived from Eq. (15)). Given the cotangent
  * g_vphi of vphi (PyTorch convention: dL/dRe + i dL/dIm), writes
  *   g_phi[k][p] = (V_x[u] g)[k][p]                       (device [nk][nphi][N_r], may be NULL)
@@ -178,6 +190,23 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
  * Synchronises the stream. */
 fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
                           double alpha, double* e_out, void* grad_psi, double grad_a[3], void* stream);
+
+/* Reverse mode of taylor_energy for the cotangent g_e of E (same arguments):
+ *   g_psi (device, may be NULL) <- g_e dE/dpsi = 2 g_e (g_s/N_k)(Omega/N_r) (T + v_loc + alpha V_x[psi]) psi
+ *   g_a   (host [3], may be NULL) <- g_e dE/d(A/c)
+ * At least one output must be given. Synchronises the stream when g_a is requested. */
+fock_status taylor_energy_vjp(fockmi_plan plan, int cell, const void* psi, const double* vloc,
+                              const double A_over_c[3], double alpha, double g_e, void* g_psi, double g_a[3],
+                              void* stream);
+
+/* Macroscopic current of Eqs. (3)-(4) in the velocity gauge (no nonlocal
+ * pseudopotential, electron charge -1):
+ *   J = -(1/Omega)(g_s/N_k) sum_{k,b} int_cell Re[psi* (-i grad + A/c) psi] dr = -(1/Omega) dE/d(A/c)
+ * (V_x does not depend on A in this gauge; only the kinetic term enters).
+ *   psi : device [nk][nb][N_r] complex128;  A_over_c : host [3];  j_out : host [3] (a.u.)
+ * Synchronises the stream. Not available for a down-sampled cell (FOCK_ERR_ARG). */
+fock_status taylor_current(fockmi_plan plan, int cell, const void* psi, const double A_over_c[3], double j_out[3],
+                           void* stream);
 
 /* Modified Gram-Schmidt in band order, per k-point, in FP64 with the cell
  * inner product (Omega/N_r) sum conj(a) b (the normalisation that Eq. (15)

@@ -6,8 +6,11 @@ Its Fourier transform is
 
     v(p) = 4 pi / |p|^2 * (1 - exp(-|p|^2 / (4 w^2))),     v(0) = pi / w^2,
 
-the p -> 0 value being the finite limit of the same expression. The factor
-1 - exp(-x) is evaluated as -expm1(-x) so that small x keeps its digits.
+the p -> 0 value being the finite limit of the same expression (the q + G = 0
+term, which the paper leaves implicit). It is used for the l = 0 slot of q = 0
+and wherever q + G is exactly zero (k and k' differing by a reciprocal-lattice
+vector of the grid). The factor 1 - exp(-x) is evaluated as -expm1(-x) so that
+small x keeps its digits.
 
 For the pair density of orbitals at k (output) and k' (occupied) the kernel is
 evaluated at q + G with q = k - k' (crystal momentum of the pair density),
@@ -64,6 +67,7 @@ def kernel_table(q, q_is_zero, n, B, omega):
         if q_is_zero:
             zero = (L1 == 0) & (L2 == 0) & (L3 == 0)
             v = np.where(zero, np.pi / (omega * omega), v)
+        v = np.where(p2 == 0.0, np.pi / (omega * omega), v)
         K += v
     # slots off Nyquist get the same value from every combination
     return K / len(combos)

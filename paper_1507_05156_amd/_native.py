@@ -27,8 +27,9 @@ FOCK_FP64 = 0
 FOCK_FP32_COMP = 1
 FOCK_FP64_FUSED = 2
 
-EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_apply_krange", "fock_energy", "fock_vjp", "taylor_step",
-           "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "fock_orthonormalize", "fock_eigensolve",
+EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_apply_krange", "fock_energy", "fock_energy_vjp",
+           "fock_vjp", "taylor_step", "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "taylor_energy_vjp",
+           "taylor_current", "fock_orthonormalize", "fock_eigensolve",
            "fock_excited_density", "fock_apply_batched", "fock_profile_enable",
            "fock_profile_read", "fock_last_error"]
 
@@ -63,11 +64,14 @@ def lib():
     L.fock_apply.argtypes = [vp, i, vp, vp, i, vp, vp]
     L.fock_apply_krange.argtypes = [vp, i, vp, i, i, vp, i, vp, vp]
     L.fock_energy.argtypes = [vp, i, vp, pd, pd, vp]
+    L.fock_energy_vjp.argtypes = [vp, i, vp, d, vp, vp]
     L.fock_vjp.argtypes = [vp, i, vp, vp, i, vp, vp, vp, vp]
     L.taylor_step.argtypes = [vp, i, vp, vp, pd, d, d, i, pd, vp]
     L.taylor_step_pc.argtypes = [vp, i, vp, vp, pd, pd, d, d, i, pd, vp]
     L.taylor_step_vjp.argtypes = [vp, i, vp, vp, pd, d, d, i, vp, vp, pd, vp]
     L.taylor_energy.argtypes = [vp, i, vp, vp, pd, d, pd, vp, pd, vp]
+    L.taylor_energy_vjp.argtypes = [vp, i, vp, vp, pd, d, d, vp, pd, vp]
+    L.taylor_current.argtypes = [vp, i, vp, pd, pd, vp]
     L.fock_orthonormalize.argtypes = [vp, i, vp, vp]
     L.fock_eigensolve.argtypes = [vp, i, vp, vp, pd, d, vp, d, i, pd, pd, C.POINTER(i), vp]
     L.fock_excited_density.argtypes = [vp, i, vp, vp, pd, vp]

@@ -147,6 +147,14 @@ class Plan:
         N.check(self._lib.fock_energy(self._h, cell, _ptr(u), C.byref(re), C.byref(im), _stream()))
         return complex(re.value, im.value)
 
+    def energy_vjp(self, u, g_e=1.0, cell=0, out=None):
+        """g_e dE_x/du (torch convention) for the cotangent g_e of E_x."""
+        c = self.cells[cell]
+        self._check(u, cell, c["nb"], "u")
+        out = torch.empty_like(u) if out is None else self._check(out, cell, c["nb"], "out")
+        N.check(self._lib.fock_energy_vjp(self._h, cell, _ptr(u), float(g_e), _ptr(out), _stream()))
+        return out
+
     def vjp(self, u, phi, g, cell=0, need_u=True, need_phi=True):
         """(g_u, g_phi) of y = V_x[u] phi for the cotangent g of y (torch convention)."""
         c = self.cells[cell]
@@ -217,17 +225,26 @@ class Plan:
                                         float(alpha), C.byref(e), _ptr(g), ga if want_grad else None, _stream()))
         return (e.value, g, np.array([ga[0], ga[1], ga[2]])) if want_grad else e.value
 
+    def energy_functional_vjp(self, psi, a_over_c, alpha, g_e=1.0, vloc=None, cell=0):
+        """(g_e dE/dpsi, g_e dE/d(A/c)) of the energy functional for its cotangent g_e."""
+        c = self.cells[cell]
+        self._check(psi, cell, c["nb"], "psi")
+        av = (C.c_double * 3)(*[float(x) for x in a_over_c])
+        g = torch.empty_like(psi)
+        ga = (C.c_double * 3)()
+        N.check(self._lib.taylor_energy_vjp(self._h, cell, _ptr(psi), _ptr(vloc) if vloc is not None else None, av,
+                                            float(alpha), float(g_e), _ptr(g), ga, _stream()))
+        return g, np.array([ga[0], ga[1], ga[2]])
+
     def current(self, psi, a_over_c, cell=0):
         """J(t) of Eqs. (3)-(4) (velocity gauge, no nonlocal pseudopotential, electron charge -1):
         -(1/Omega) (g_s/N_k) sum_{k,b} int_cell Re[psi* (-i grad + A/c) psi] dr = -(1/Omega) dE/d(A/c)."""
         c = self.cells[cell]
         self._check(psi, cell, c["nb"], "psi")
         av = (C.c_double * 3)(*[float(x) for x in a_over_c])
-        e = C.c_double()
-        ga = (C.c_double * 3)()
-        # alpha = 0: V_x does not depend on A in the velocity gauge, so only the kinetic term is needed
-        N.check(self._lib.taylor_energy(self._h, cell, _ptr(psi), None, av, 0.0, C.byref(e), None, ga, _stream()))
-        return -np.array([ga[0], ga[1], ga[2]]) / c["vol"]
+        j = (C.c_double * 3)()
+        N.check(self._lib.taylor_current(self._h, cell, _ptr(psi), av, j, _stream()))
+        return np.array([j[0], j[1], j[2]])
 
     def orthonormalize(self, psi, cell=0):
         c = self.cells[cell]

@@ -1,9 +1,9 @@
 """torch.autograd.Function wrappers over the HIP library (hand-written adjoints).
 
   FockApply          y = V_x[u] phi                    backward: fock_vjp
-  FockEnergy         E_x[u]                            backward: 2 (g_s/N_k)(Omega/N_r) V_x[u] u
+  FockEnergy         E_x[u]                            backward: fock_energy_vjp
   TaylorStep         psi(t+dt) = T4(-i dt h) psi(t)    backward: taylor_step_vjp
-  EnergyFunctional   E[psi; A/c]                       backward: taylor_energy gradients
+  EnergyFunctional   E[psi; A/c]                       backward: taylor_energy_vjp
   propagate          N Taylor steps under the sin^2 pulse of Eq. (21), checkpointed every
                      `checkpoint_every` steps, returning psi(t_N) and E_ex = E(t_N) - E(t_0)
 
@@ -48,16 +48,7 @@ class FockEnergy(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (u,) = ctx.saved_tensors
-        c = ctx.plan.cells[ctx.cell]
-        w = (c["gs"] / 2.0) / c["nk"] * c["vol"] / c["nr"]
-        v = ctx.plan.apply(u, None, ctx.cell)
-        if c.get("src") is None:
-            # V_x Hermitian and symmetric in its two occurrences of u: grad = 4 w V_x u
-            return v * (4.0 * w * float(g)), None, None
-        # down-sampled: 2 w V_x u from the targets, plus the adjoint through the
-        # source orbitals with cotangent w u
-        gu, _ = ctx.plan.vjp(u, u, u * w, ctx.cell, need_u=True, need_phi=False)
-        return (v * (2.0 * w) + gu) * float(g), None, None
+        return ctx.plan.energy_vjp(u.contiguous(), float(g), ctx.cell), None, None
 
 
 class TaylorStep(torch.autograd.Function):
@@ -92,10 +83,9 @@ class EnergyFunctional(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (psi,) = ctx.saved_tensors
-        _, gpsi, ga = ctx.plan.energy_functional(psi.contiguous(), ctx.a, ctx.alpha, vloc=ctx.vloc, cell=ctx.cell,
-                                                 want_grad=True)
-        gf = float(g)
-        return gpsi * gf, torch.tensor(ga * gf, dtype=torch.float64), None, None, None, None
+        gpsi, ga = ctx.plan.energy_functional_vjp(psi.contiguous(), ctx.a, ctx.alpha, float(g), vloc=ctx.vloc,
+                                                  cell=ctx.cell)
+        return gpsi, torch.tensor(ga, dtype=torch.float64), None, None, None, None
 
 
 def fock_apply(u, phi, plan, cell=0):

@@ -505,6 +505,43 @@ fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* e
   return FOCK_OK;
 }
 
+fock_status fock_energy_vjp(fockmi_plan plan, int cell, const void* u_occ, double g_e, void* g_u_occ, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = p->check_ready(cell);
+  if (s != FOCK_OK) return s;
+  Cell& c = p->cells[cell];
+  if (!u_occ || !g_u_occ) return fail(FOCK_ERR_ARG, "NULL device pointer");
+  if (!aligned16(u_occ) || !aligned16(g_u_occ)) return fail(FOCK_ERR_ARG, "device pointers must be 16-byte aligned");
+  if (!std::isfinite(g_e)) return fail(FOCK_ERR_ARG, "g_e is not finite");
+  const size_t bu = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
+  if (overlap(g_u_occ, bu, u_occ, bu)) return fail(FOCK_ERR_ARG, "g_u_occ overlaps u_occ");
+  hipStream_t st = (hipStream_t)stream;
+  const c128* U = (const c128*)u_occ;
+  c128* GU = (c128*)g_u_occ;
+  // E_x = w sum conj(u) V_x[u] u, w = (g_s/2)(1/N_k)(Omega/N_r). u enters as the
+  // target (conj(u) and u outside the pair sum) and as the source orbitals; the
+  // target occurrences give 2 w V_x u, the source occurrences the source-side
+  // adjoint with cotangent w u, which equals 2 w V_x u when every k-point is a source.
+  const double cw = g_e * (c.gs / 2.0) / c.nk * c.vol / c.nr;
+  const c128* Us = nullptr;
+  if ((s = p->sources(c, U, c.nb, p->srcbuf, st, &Us)) != FOCK_OK) return s;
+  if (!c.ds) return p->general(c, c.fwd(), U, c.nb, Us, Us, c.nb, GU, -4.0 * cw / c.nsrc, false, st);
+  if ((s = p->general(c, c.fwd(), U, c.nb, Us, Us, c.nb, GU, -2.0 * cw / c.nsrc, false, st)) != FOCK_OK) return s;
+  // source side: -(1/|S|) sum_{k,i} 2 (w u_ik) W_{k'-k}(conj(u_ik) u_jk') for k' in S
+  const size_t block = (size_t)c.nb * c.nr;
+  if ((s = p->srcout.ensure((size_t)c.nsrc * block * sizeof(c128), p->workspace_cap, "source gradient")) != FOCK_OK)
+    return s;
+  c128* gs = (c128*)p->srcout.ptr;
+  if ((s = p->general(c, c.rev(), Us, c.nb, U, U, c.nb, gs, -2.0 * cw / c.nsrc, false, st)) != FOCK_OK) return s;
+  for (int i = 0; i < c.nsrc; ++i) {
+    hipError_t e = launch_scale_add(GU + (size_t)c.src[i] * block, gs + (size_t)i * block, 1.0, 0.0, (long)block, st);
+    if (e != hipSuccess) return hip_fail(e, "add source gradient");
+  }
+  return FOCK_OK;
+}
+
 fock_status fock_vjp(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi, const void* g_vphi,
                      void* g_u_occ, void* g_phi, void* stream) {
   g_last_error.clear();

@@ -267,34 +267,43 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
   return FOCK_OK;
 }
 
-fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
-                          double alpha, double* e_out, void* grad_psi, double grad_a[3], void* stream) {
-  Plan* p = nullptr;
-  fock_status s = common_checks(plan, cell, &p);
-  if (s != FOCK_OK) return s;
-  Cell& c = p->cells[cell];
-  if (c.ds) return fail(FOCK_ERR_ARG, "taylor_energy is not available for a down-sampled cell");
-  if (!psi || !A_over_c || !e_out) return fail(FOCK_ERR_ARG, "NULL pointer");
+}  // extern "C"
+
+namespace {
+
+// E = (g_s/N_k)(Omega/N_r) sum conj(psi) (T[a] + v_loc) psi + alpha E_x[psi] (into *e_out when
+// given), and the gradients times the cotangent g_e: grad_psi <- g_e dE/dpsi (PyTorch
+// convention, 2 (g_s/N_k)(Omega/N_r) (T + v_loc + alpha V_x[psi]) psi) and grad_a <- g_e dE/d(A/c).
+fock_status energy_impl(Plan* p, Cell& c, const void* psi, const double* vloc, const double A_over_c[3], double alpha,
+                        double g_e, double* e_out, void* grad_psi, double grad_a[3], hipStream_t st) {
+  if (c.ds) return fail(FOCK_ERR_ARG, "the energy functional is not available for a down-sampled cell");
+  if (!psi || !A_over_c) return fail(FOCK_ERR_ARG, "NULL pointer");
   if (!aligned16(psi) || (grad_psi && !aligned16(grad_psi))) return fail(FOCK_ERR_ARG, "misaligned pointer");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(A_over_c[d])) return fail(FOCK_ERR_ARG, "A_over_c is not finite");
   const size_t bytes = (size_t)c.nk * c.nb * c.nr * sizeof(c128);
   if (grad_psi && overlap(grad_psi, bytes, psi, bytes)) return fail(FOCK_ERR_ARG, "grad_psi overlaps psi");
-  hipStream_t st = (hipStream_t)stream;
   const long count = (long)c.nk * c.nb * c.nr;
-  if ((s = p->field_bufs(c, {&p->lam}, c.nb)) != FOCK_OK) return s;
-  c128* hpsi = (c128*)p->lam.ptr;
-  const c128* P = (const c128*)psi;
-  if ((s = p->h_apply(c, P, nullptr, P, hpsi, nullptr, 1.0, 0.0, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
-  double hre, him, xre = 0.0, xim = 0.0;
-  if ((s = p->dot(P, hpsi, count, st, &hre, &him)) != FOCK_OK) return s;
-  if (alpha != 0.0 && (s = p->dot(P, (const c128*)p->vxb.ptr, count, st, &xre, &xim)) != FOCK_OK) return s;
   const double w = c.gs / c.nk * c.vol / c.nr;
-  // sum conj(psi) h psi counts V_x with alpha; the energy counts it with alpha / 2
-  *e_out = w * (hre - 0.5 * alpha * xre);
+  const c128* P = (const c128*)psi;
+  fock_status s;
   hipError_t e;
-  if (grad_psi) {
-    if ((e = hipMemsetAsync(grad_psi, 0, bytes, st)) != hipSuccess) return hip_fail(e, "zero");
-    if ((e = launch_scale_add((c128*)grad_psi, hpsi, 2.0 * w, 0.0, count, st)) != hipSuccess)
-      return hip_fail(e, "gradient");
+  if (e_out || grad_psi) {
+    if ((s = p->field_bufs(c, {&p->lam}, c.nb)) != FOCK_OK) return s;
+    c128* hpsi = (c128*)p->lam.ptr;
+    if ((s = p->h_apply(c, P, nullptr, P, hpsi, nullptr, 1.0, 0.0, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
+    if (e_out) {
+      double hre, him, xre = 0.0, xim = 0.0;
+      if ((s = p->dot(P, hpsi, count, st, &hre, &him)) != FOCK_OK) return s;
+      if (alpha != 0.0 && (s = p->dot(P, (const c128*)p->vxb.ptr, count, st, &xre, &xim)) != FOCK_OK) return s;
+      // sum conj(psi) h psi counts V_x with alpha; the energy counts it with alpha / 2
+      *e_out = w * (hre - 0.5 * alpha * xre);
+    }
+    if (grad_psi) {
+      if ((e = launch_zero((c128*)grad_psi, count, st)) != hipSuccess) return hip_fail(e, "zero");
+      if ((e = launch_scale_add((c128*)grad_psi, hpsi, 2.0 * w * g_e, 0.0, count, st)) != hipSuccess)
+        return hip_fail(e, "gradient");
+    }
   }
   if (grad_a) {
     const int nblk = 512;
@@ -311,8 +320,47 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
     if ((e = hipMemcpyAsync(red, p->red6.ptr, sizeof(red), hipMemcpyDeviceToHost, st)) != hipSuccess)
       return hip_fail(e, "copy");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync");
-    for (int d = 0; d < 3; ++d) grad_a[d] = w * red[2 * d] / c.nr;
+    for (int d = 0; d < 3; ++d) grad_a[d] = g_e * w * red[2 * d] / c.nr;
   }
+  return FOCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
+                          double alpha, double* e_out, void* grad_psi, double grad_a[3], void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  if (!e_out) return fail(FOCK_ERR_ARG, "e_out is NULL");
+  return energy_impl(p, p->cells[cell], psi, vloc, A_over_c, alpha, 1.0, e_out, grad_psi, grad_a, (hipStream_t)stream);
+}
+
+fock_status taylor_energy_vjp(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
+                              double alpha, double g_e, void* g_psi, double g_a[3], void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  if (!std::isfinite(g_e)) return fail(FOCK_ERR_ARG, "g_e is not finite");
+  if (!g_psi && !g_a) return fail(FOCK_ERR_ARG, "both outputs are NULL");
+  return energy_impl(p, p->cells[cell], psi, vloc, A_over_c, alpha, g_e, nullptr, g_psi, g_a, (hipStream_t)stream);
+}
+
+fock_status taylor_current(fockmi_plan plan, int cell, const void* psi, const double A_over_c[3], double j_out[3],
+                           void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  if (!j_out) return fail(FOCK_ERR_ARG, "j_out is NULL");
+  Cell& c = p->cells[cell];
+  // J = -(1/Omega) dE/d(A/c); V_x does not depend on A in the velocity gauge, so
+  // only the kinetic term enters (alpha = 0)
+  double ga[3];
+  if ((s = energy_impl(p, c, psi, nullptr, A_over_c, 0.0, 1.0, nullptr, nullptr, ga, (hipStream_t)stream)) != FOCK_OK)
+    return s;
+  for (int d = 0; d < 3; ++d) j_out[d] = -ga[d] / c.vol;
   return FOCK_OK;
 }
 

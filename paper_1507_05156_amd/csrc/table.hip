@@ -3,8 +3,10 @@
 // v(p) = 4 pi/|p|^2 * (1 - exp(-|p|^2 / 4 w^2)), computed as -expm1 so that
 // small |p| keeps its digits; v(0) = pi / w^2, the finite limit, used for the
 // q = 0, l = 0 slot (q = 0 is an integer flag set by the host when the two
-// k-points are the same entry of the mesh). Nyquist slots (l_d = -n_d/2 for
-// even n_d) take the average of v over l_d = +-n_d/2, over all such axes.
+// k-points are the same entry of the mesh) and wherever q + G is exactly zero
+// (two k-points that differ by a reciprocal-lattice vector of the grid). Nyquist
+// slots (l_d = -n_d/2 for even n_d) take the average of v over l_d = +-n_d/2,
+// over all such axes.
 #include "kernels.hpp"
 
 namespace fockmi {
@@ -50,7 +52,7 @@ __global__ void build_table_f64_kernel(double* __restrict__ K, const double* __r
     const double py = qy + lf[0] * g.B[0][1] + lf[1] * g.B[1][1] + lf[2] * g.B[2][1];
     const double pz = qz + lf[0] * g.B[0][2] + lf[1] * g.B[1][2] + lf[2] * g.B[2][2];
     const double p2 = px * px + py * py + pz * pz;
-    sum += g0 ? M_PI / (omega * omega) : v_screened(p2, omega);
+    sum += (g0 || p2 == 0.0) ? M_PI / (omega * omega) : v_screened(p2, omega);
     ++count;
   }
   K[(long)q * nr + idx] = scale * (sum / count);

@@ -90,6 +90,10 @@ def test_null_arguments():
         == N.FOCK_ERR_ARG
     nex = C.c_double()
     assert lib.fock_excited_density(None, 0, None, None, C.byref(nex), None) == N.FOCK_ERR_ARG
+    assert lib.fock_energy_vjp(None, 0, None, 1.0, None, None) == N.FOCK_ERR_ARG
+    j = (C.c_double * 3)()
+    assert lib.taylor_energy_vjp(None, 0, None, None, a, 0.25, 1.0, None, j, None) == N.FOCK_ERR_ARG
+    assert lib.taylor_current(None, 0, None, a, j, None) == N.FOCK_ERR_ARG
     assert b"plan is NULL" in lib.fock_last_error()
     assert lib.fock_plan_destroy(None) == N.FOCK_OK
 

@@ -66,3 +66,52 @@ def test_work_route_converges_linearly_to_the_energy_route():
         assert abs(e_ex) > 1e-6
     ratio = diffs[0] / diffs[1]
     assert 1.6 < ratio < 2.4, (diffs, ratio)
+
+
+def _pulse_closed_form(t, A0, omega_l, Td):
+    """Eq. (21) with the envelope written through the double-angle identity
+    sin^2(x) = (1 - cos 2x) / 2, a form independent of the implementations."""
+    if not 0.0 < t < Td:
+        return 0.0
+    return -A0 * np.cos(omega_l * t) * 0.5 * (1.0 - np.cos(2.0 * np.pi * t / Td))
+
+
+def _pulse_implementations():
+    from paper_1507_05156_amd import dynamics
+    yield "oracle", lambda t, A0, w, Td: otaylor.pulse_a_over_c(t, A0, w, Td)
+    yield "dynamics", lambda t, A0, w, Td: dynamics.pulse_a_over_c(t, A0, w, Td)
+    try:
+        import torch
+        from paper_1507_05156_amd import autograd as ag
+    except ImportError:
+        return
+    yield "autograd", lambda t, A0, w, Td: ag.pulse_a_over_c(t, torch.tensor(A0, dtype=torch.float64), w, Td).numpy()
+
+
+def test_pulse_follows_eq21():
+    """A(t)/c = -A0 cos(w_L t) sin^2(pi t/T_d) e_z on (0, T_d), zero outside, for the
+    oracle's pulse and both pulses of the package: the vanishing ends, the value at the
+    window's centre, the envelope's mirror symmetry, the carrier's period and the
+    closed form above all fix the shape, the sign and the carrier."""
+    A0, Td = 0.05, 0.4
+    for name, f in _pulse_implementations():
+        for t in (-0.1, 0.0, Td, Td + 0.05):
+            assert np.all(f(t, A0, OMEGA_L, Td) == 0.0), (name, t)
+        mid = f(Td / 2, A0, OMEGA_L, Td)
+        assert np.allclose(mid, [0.0, 0.0, -A0 * np.cos(OMEGA_L * Td / 2)], rtol=1e-14, atol=0), name
+        for t in (0.013, 0.07, 0.151, 0.29, 0.3999):
+            a = f(t, A0, OMEGA_L, Td)
+            assert a[0] == 0.0 and a[1] == 0.0, name
+            assert np.isclose(a[2], _pulse_closed_form(t, A0, OMEGA_L, Td), rtol=1e-13, atol=1e-18), (name, t)
+            # envelope a(t) / (-A0 cos(w_L t)) mirrored about T_d / 2
+            env = a[2] / (-A0 * np.cos(OMEGA_L * t))
+            env_m = f(Td - t, A0, OMEGA_L, Td)[2] / (-A0 * np.cos(OMEGA_L * (Td - t)))
+            assert np.isclose(env, env_m, rtol=1e-12), (name, t)
+            assert 0.0 < env < 1.0
+        # carrier period 2 pi / w_L: on a window long enough to hold several periods, the
+        # ratio a(t + P) / a(t) is the ratio of the envelopes alone
+        Tl = 3000.0
+        P = 2.0 * np.pi / OMEGA_L
+        for t in (100.0, 512.5, 1700.0):
+            r = f(t + P, A0, OMEGA_L, Tl)[2] / f(t, A0, OMEGA_L, Tl)[2]
+            assert np.isclose(r, np.sin(np.pi * (t + P) / Tl) ** 2 / np.sin(np.pi * t / Tl) ** 2, rtol=1e-9), name

@@ -83,6 +83,25 @@ def test_kernel_nyquist_symmetry_and_g0(n):
     assert np.all(K0 > 0)
 
 
+@pytest.mark.parametrize("n", [(6, 6, 6), (8, 8, 8)])
+def test_kernel_reciprocal_lattice_shift(n):
+    """k' = k + b_1 is the same crystal momentum as k: K_{-b1}[l] = v(G_{l - e1}) = K_0[l - e1]
+    away from the Nyquist slots, including the finite q + G = 0 value pi/w^2 at l = e1."""
+    B = oracle.reciprocal(CELL)
+    K0 = oracle.kernel_table(np.zeros(3), True, n, B, OMEGA)
+    Ks = oracle.kernel_table(-B[0], False, n, B, OMEGA)
+    assert np.all(np.isfinite(Ks))
+    assert Ks[1, 0, 0] == pytest.approx(np.pi / OMEGA ** 2, rel=1e-15)
+    from oracle.lattice import fftfreq_int
+    l1 = fftfreq_int(n[0])
+    for j1 in range(n[0]):
+        if l1[j1] - 1 <= -n[0] // 2 or l1[j1] == -n[0] // 2:
+            continue   # l - e1 would leave the grid's G set or start from the Nyquist slot
+        j0 = int(np.nonzero(l1 == l1[j1] - 1)[0][0])
+        inner = (slice(0, n[1] // 2), slice(0, n[2] // 2))
+        assert np.allclose(Ks[j1][inner], K0[j0][inner], rtol=1e-13, atol=0), j1
+
+
 # ------------------------------------------------ Gaussian-Wannier closed form
 @pytest.mark.parametrize("nkm,n,tol", [(1, 32, 1e-10), (2, 32, 1e-13), (2, 24, 1e-11)])
 def test_gaussian_wannier_closed_form(nkm, n, tol):
