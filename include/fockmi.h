@@ -259,6 +259,23 @@ fock_status fock_excited_density(fockmi_plan plan, int cell, const void* phi, co
 fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const void* const* phi,
                                const int* nphi, void* const* vphi, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): fock_apply
+ * for a FOCK_FP32_COMP plan with the same arguments and result, which calls no
+ * hipMalloc, hipFree or other allocating routine. Its scratch (the complex64
+ * shadows of u_occ and phi, the Neumaier compensation field and, for 32^3 cells,
+ * the FP32 band sums) comes from one fixed device array of 64 MiB that the
+ * library holds on every GPU it runs on until the process ends. It runs the
+ * grid form of the fused kernel (one workgroup per target), so for grid
+ * lengths up to 24 it gives fock_apply's bits.
+ * Errors: FOCK_ERR_SIZE when the cell needs more scratch than the fixed array
+ * (about 32 MiB of shadows: e.g. 16^3 with up to ~500 orbitals); FOCK_ERR_ARG as
+ * fock_apply, and for a plan of another precision. Every call on one GPU uses
+ * that GPU's one array: calls that overlap in time on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. Stream-ordered. */
+fock_status fock_apply_noalloc(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
+                               void* vphi, void* stream);
+
 /* Diagnostics for measurement. While enabled, every launch of the fused pair
  * kernel (FOCK_FP32_COMP plans) and every batch of the plain path's pair
  * pipeline (FOCK_FP64 plans) is bracketed by HIP events recorded on the

@@ -408,6 +408,12 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
     delete p;
     return fail(FOCK_ERR_HIP, "hipGetDevice failed");
   }
+  if (noalloc_setup(p->device) != FOCK_OK) {
+    std::string msg = g_last_error;
+    delete p;
+    g_last_error = msg;
+    return FOCK_ERR_HIP;
+  }
   if (tune_cache_json) {
     p->tune_path = tune_cache_json;
     p->tuning = true;

@@ -14,6 +14,8 @@
 namespace fockmi {
 
 fock_status fail(fock_status st, const char* fmt, ...);
+// looks up the current device's copy of the allocation-free call's scratch array (noalloc.hip)
+fock_status noalloc_setup(int device);
 fock_status hip_fail(hipError_t e, const char* where);
 
 // device allocation owned by the plan, grown on demand
