@@ -37,7 +37,8 @@ COUNTER_TRAFFIC = {
     "fetch_kib": 3690581130.6875, "write_kib": 3822679184.0,
     "fetch_scale": 1.9998827049385512, "write_scale": 1.0,
 }
-KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/fft_reg.hpp",
+KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/split32.hip",
+                  "paper_1507_05156_amd/csrc/fft_reg.hpp",
                   "paper_1507_05156_amd/csrc/fused_common.hpp", "paper_1507_05156_amd/csrc/kernels.hpp")
 
 
@@ -507,7 +508,7 @@ def main():
                    "pairs_per_step": pairs, "ffts_per_step": 2 * pairs, "kernel": "fused FP32 pair kernel"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"fused_lockstep_kernel<{n}>" if n == 32 else f"fused_apply_kernel<{n}>", "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,
+                     "kernel": "split32_kernel" if n == 32 else f"fused_apply_kernel<{n}>", "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,
                      "alg_bytes_per_pair": nr * 8, "alg_bytes_per_launch": alg_bytes, "pairs_per_launch": pairs,
                      "traffic_bytes_per_pair": traffic / pairs if traffic else None,
                      "traffic_GBs": traffic / kern_avg_s / 1e9 if traffic else None,

@@ -285,6 +285,13 @@ fock_status fock_apply_noalloc(fockmi_plan plan, int cell, const void* u_occ, co
 fock_status fock_profile_enable(fockmi_plan plan, int enable);
 fock_status fock_profile_read(fockmi_plan plan, double* kernel_ms, long long* launches, int reset);
 
+/* Diagnostics of the split 32^3 form of the FP32 fused kernel (one target on two
+ * CUs of one XCD): the number of its launches, counted while profiling is
+ * enabled, that stopped (a rendezvous timed out or the pair's CUs sat on two
+ * XCDs) and whose result therefore came from the one-CU lockstep form launched
+ * behind it. Synchronises the device; reset=1 clears the count. */
+fock_status fock_profile_fallbacks(fockmi_plan plan, long long* count, int reset);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* fock_last_error(void);
 

@@ -30,7 +30,7 @@ FOCK_FP64_FUSED = 2
 EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_apply_krange", "fock_energy", "fock_energy_vjp",
            "fock_vjp", "taylor_step", "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "taylor_energy_vjp",
            "taylor_current", "fock_orthonormalize", "fock_eigensolve",
-           "fock_excited_density", "fock_apply_batched", "fock_apply_noalloc", "fock_profile_enable",
+           "fock_excited_density", "fock_apply_batched", "fock_apply_noalloc", "fock_profile_enable", "fock_profile_fallbacks",
            "fock_profile_read", "fock_last_error"]
 
 
@@ -79,6 +79,7 @@ def lib():
     L.fock_apply_noalloc.argtypes = [vp, i, vp, vp, i, vp, vp]
     L.fock_profile_enable.argtypes = [vp, i]
     L.fock_profile_read.argtypes = [vp, pd, C.POINTER(C.c_longlong), i]
+    L.fock_profile_fallbacks.argtypes = [vp, C.POINTER(C.c_longlong), i]
     L.fock_last_error.argtypes = []
     L.fock_last_error.restype = C.c_char_p
     for name in EXPORTS[:-1]:

@@ -112,6 +112,12 @@ class Plan:
         N.check(self._lib.fock_profile_read(self._h, C.byref(ms), C.byref(n), 1 if reset else 0))
         return ms.value, n.value
 
+    def profile_fallbacks(self, reset=True):
+        """Split 32^3 launches (counted while profiling) whose result came from the lockstep form."""
+        n = C.c_longlong()
+        N.check(self._lib.fock_profile_fallbacks(self._h, C.byref(n), 1 if reset else 0))
+        return n.value
+
     # ------------------------------------------------------------- operations
     def apply(self, u, phi=None, cell=0, out=None):
         """V_x[u] phi (phi defaults to u)."""

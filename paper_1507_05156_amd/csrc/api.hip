@@ -183,11 +183,21 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     return s;
   }
   const int nitems = ps.ntk * nx;
+  const int n = c.geom.n1;
   // the lockstep form runs one workgroup per CU (a multiple of 8: one share per XCD)
   LockstepCfg ls{nullptr, (num_cus / 8) * 8};
-  const bool has_ls = fused_has_lockstep(c.geom.n1) && ls.nwg >= 8;
-  // its k' split: the part count (dividing the source k-points, at most 4) with
-  // the fewest rounds of ls.nwg workgroups, in units of a whole target's sum
+  const bool has_ls = fused_has_lockstep(n) && ls.nwg >= 8;
+  // the split 32^3 form runs one workgroup per CU, two per target (a multiple of 16)
+  const int nwg_split = (num_cus / 16) * 16;
+  const bool has_split = n == 32 && c.SD.ptr && nwg_split >= 16 && has_ls && !accumulate;
+  auto usable = [&](int v) {
+    if (n != 32) return v >= 0 && v < fused_variants(n);
+    return v == 0 || (v == 1 && has_ls) || (v == 2 && has_split);
+  };
+  auto fallback_variant = [&](int v) { return usable(v) ? v : (n == 32 && has_ls ? 1 : 0); };
+  // the lockstep form's k' split: the part count (dividing the source k-points,
+  // at most 4) with the fewest rounds of ls.nwg workgroups, in units of a whole
+  // target's sum
   int ksplit = 1;
   if (has_ls) {
     if ((s = sync.ensure(kLockstepInts * sizeof(int), workspace_cap, "lockstep counters")) != FOCK_OK) return s;
@@ -202,15 +212,6 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
       }
     }
   }
-  if ((s = comp.ensure((size_t)ksplit * nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
-    return s;
-  if (ksplit > 1 &&
-      (s = parts.ensure((size_t)(ksplit - 1) * nitems * nr * sizeof(c128), workspace_cap, "k' part sums")) != FOCK_OK)
-    return s;
-  const size_t acc_elems = fused_acc_scratch_elems(c.geom.n1, std::max(nitems, ls.nwg));
-  if (acc_elems && (s = accs.ensure(acc_elems * sizeof(c64), workspace_cap, "FP32 partial sums")) != FOCK_OK)
-    return s;
-  const int nvar = fused_variants(c.geom.n1) - (fused_has_lockstep(c.geom.n1) && !has_ls ? 1 : 0);
   FusedArgs a{};
   a.X = Xs;
   a.P = Ps;
@@ -218,8 +219,6 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   a.Kt = (const float*)c.Kt.ptr;
   a.qidx = ps.qidx;
   a.out = out;
-  a.comp = (c64*)comp.ptr;
-  a.accs = (c64*)accs.ptr;
   a.nk = ps.nsk;
   a.nx = nx;
   a.nb = ns;
@@ -228,30 +227,84 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   a.scale = scale;
   a.accumulate = accumulate ? 1 : 0;
   a.xcd_map = xcd_map;
-  a.n = c.geom.n1;
-  a.ksplit = ksplit;
-  a.part_out = ksplit > 1 ? (c128*)parts.ptr : nullptr;
-  int variant = fused_default_variant(c.geom.n1);
-  if (variant >= nvar) variant = 0;
+  a.n = n;
+  a.ksplit = 1;
+  a.part_out = nullptr;
+  a.gate = nullptr;
+  // buffers of one variant (grown on demand, kept by the plan)
+  auto prepare = [&](int v) -> fock_status {
+    fock_status st2;
+    const int h = v == 1 ? ksplit : 1;
+    if ((st2 = comp.ensure((size_t)h * nitems * nr * sizeof(c64), workspace_cap, "compensation buffer")) != FOCK_OK)
+      return st2;
+    if (h > 1 && (st2 = parts.ensure((size_t)(h - 1) * nitems * nr * sizeof(c128), workspace_cap, "k' part sums")) !=
+                     FOCK_OK)
+      return st2;
+    const size_t acc_elems = fused_acc_scratch_elems(n, v == 0 ? nitems : ls.nwg);
+    if (acc_elems && (st2 = accs.ensure(acc_elems * sizeof(c64), workspace_cap, "FP32 partial sums")) != FOCK_OK)
+      return st2;
+    if (v == 2) {
+      if ((st2 = xbuf.ensure(split32_xbuf_elems(nwg_split) * sizeof(c64), workspace_cap, "exchange buffers")) !=
+          FOCK_OK)
+        return st2;
+      if ((st2 = sflags.ensure(split32_flag_ints(nwg_split) * sizeof(int), workspace_cap, "rendezvous counters")) !=
+          FOCK_OK)
+        return st2;
+      if ((st2 = sstatus.ensure(sizeof(int), workspace_cap, "abort word")) != FOCK_OK) return st2;
+      if (!fallbacks.ptr) {
+        if ((st2 = fallbacks.ensure(sizeof(long long), workspace_cap, "fallback count")) != FOCK_OK) return st2;
+        hipError_t e2 = launch_zero_ll((long long*)fallbacks.ptr, st);
+        if (e2 != hipSuccess) return hip_fail(e2, "fallback count");
+      }
+    }
+    a.comp = (c64*)comp.ptr;
+    a.accs = (c64*)accs.ptr;
+    a.ksplit = h;
+    a.part_out = h > 1 ? (c128*)parts.ptr : nullptr;
+    return FOCK_OK;
+  };
+  // one application in variant v
+  auto launch = [&](int v) -> hipError_t {
+    if (v != 2) return launch_fused_apply(n, a, st, v, &ls);
+    SplitArgs sa{};
+    sa.f = a;
+    sa.SD = (const float*)c.SD.ptr;
+    sa.xbuf = (c64*)xbuf.ptr;
+    sa.flags = (int*)sflags.ptr;
+    sa.status = (int*)sstatus.ptr;
+    sa.band_flush = band_flush;
+    sa.wait_ticks = split_wait_ticks;
+    hipError_t e2 = launch_split32(sa, nwg_split, st);
+    if (e2 != hipSuccess) return e2;
+    // the lockstep form behind it, run only if the split launch stopped
+    FusedArgs fb = a;
+    fb.gate = (const int*)sstatus.ptr;
+    if ((e2 = launch_fused_apply(n, fb, st, 1, &ls)) != hipSuccess) return e2;
+    if (profiling) e2 = launch_count_abort((long long*)fallbacks.ptr, (const int*)sstatus.ptr, st);
+    return e2;
+  };
+  int variant = fallback_variant(fused_default_variant(n));
   hipError_t e;
   const std::string key = key_for(c, ps, nx, "fused");
   TuneEntry te;
   if (tune.get(key, &te)) {
-    variant = (int)te.fields["variant"];
+    variant = fallback_variant((int)te.fields["variant"]);
     a.xcd_map = (int)te.fields["xcd_map"];
-    if (variant >= nvar) variant = 0;
   } else if (tuning && !accumulate) {
-    // measure every candidate on this call's data (each writes the same result)
+    // measure every candidate on this call's data (each writes the same result up
+    // to the grouping of its FP64 additions); the XCD map matters only for the grid form
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tuning event");
     if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
     double best = 1e300;
     int bv = 0, bx = 1;
-    for (int v = 0; v < nvar; ++v) {
-      for (int x = 0; x < 2; ++x) {
-        a.xcd_map = x;
+    for (int v = 0; v < fused_variants(n); ++v) {
+      if (!usable(v)) continue;
+      if ((s = prepare(v)) != FOCK_OK) return s;
+      for (int x = 0; x < ((n != 32 || v == 0) ? 2 : 1); ++x) {
+        a.xcd_map = (n != 32 || v == 0) ? x : 1;
         (void)hipEventRecord(e0, st);
-        if ((e = launch_fused_apply(c.geom.n1, a, st, v, &ls)) != hipSuccess) return hip_fail(e, "fused pair kernel");
+        if ((e = launch(v)) != hipSuccess) return hip_fail(e, "fused pair kernel");
         (void)hipEventRecord(e1, st);
         if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
         float ms = 0.f;
@@ -259,7 +312,7 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
         if (ms < best) {
           best = ms;
           bv = v;
-          bx = x;
+          bx = a.xcd_map;
         }
       }
     }
@@ -273,9 +326,9 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     variant = bv;
     a.xcd_map = bx;
   }
+  if ((s = prepare(variant)) != FOCK_OK) return s;
   if ((e = prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
-  if ((e = launch_fused_apply(c.geom.n1, a, st, variant, &ls)) != hipSuccess)
-    return hip_fail(e, "fused pair kernel");
+  if ((e = launch(variant)) != hipSuccess) return hip_fail(e, "fused pair kernel");
   if ((e = prof_end(st)) != hipSuccess) return hip_fail(e, "profile event");
   return FOCK_OK;
 }
@@ -420,6 +473,8 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
     (void)p->tune.load(p->tune_path);
   }
   if (const char* g = std::getenv("FOCKMI_GRAPH")) p->use_graph = std::atoi(g) != 0;
+  if (const char* g = std::getenv("FOCKMI_BAND_FLUSH")) p->band_flush = std::max(1, std::atoi(g));
+  if (const char* g = std::getenv("FOCKMI_SPLIT_WAIT_TICKS")) p->split_wait_ticks = std::atol(g);
   {
     hipDeviceProp_t prop;
     p->num_cus = hipGetDeviceProperties(&prop, p->device) == hipSuccess ? prop.multiProcessorCount : 256;
@@ -611,6 +666,26 @@ fock_status fock_profile_enable(fockmi_plan plan, int enable) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (p->magic != Plan::kMagic) return fail(FOCK_ERR_STATE, "plan is not valid (destroyed or corrupt)");
   p->profiling = enable != 0;
+  return FOCK_OK;
+}
+
+fock_status fock_profile_fallbacks(fockmi_plan plan, long long* count, int reset) {
+  g_last_error.clear();
+  if (!plan) return fail(FOCK_ERR_ARG, "plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->magic != Plan::kMagic) return fail(FOCK_ERR_STATE, "plan is not valid (destroyed or corrupt)");
+  long long n = 0;
+  hipError_t e;
+  if (p->fallbacks.ptr) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "sync");
+    if ((e = hipMemcpy(&n, p->fallbacks.ptr, sizeof(n), hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "read fallback count");
+    if (reset) {
+      if ((e = launch_zero_ll((long long*)p->fallbacks.ptr, nullptr)) != hipSuccess) return hip_fail(e, "reset");
+      if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "sync");
+    }
+  }
+  if (count) *count = n;
   return FOCK_OK;
 }
 

@@ -6,9 +6,9 @@
 // does the inverse FFT and accumulates M_jk' * W. The band sum over j is kept
 // in FP32 (in registers for N <= 24; for N = 32, whose working field alone
 // fills half the register file, in a per-workgroup global buffer); after every
-// k' the FP32 partial sum is added to an FP64 running sum with Neumaier
-// compensation (the compensation term stored in FP32), and the final FP64
-// value is s + c.
+// 16 bands and at the end of every k' the FP32 partial sum is added to an FP64
+// running sum with Neumaier compensation (the compensation term stored in
+// FP32), and the final FP64 value is s + c.
 //
 // At N = 32 a persistent form runs one workgroup per CU and keeps the
 // workgroups of each XCD in step pair by pair (fused_lockstep_kernel), so that
@@ -66,6 +66,10 @@ constexpr int grp_m() { return N == 16 ? 8 : (N <= 24 ? 4 : 0); }
 // element, with the loads skipped where the flags make them unused).
 template <int N>
 constexpr int flush_depth() { return N == 32 ? 4 : 0; }
+
+// bands per FP32 partial sum before it is folded into the FP64 running sum: the
+// FP32 rounding of the band sum stays that of at most 16 terms for any band count
+constexpr int kBandFlush = 16;
 
 template <int N>
 constexpr int fused_lds_elems() {
@@ -213,8 +217,13 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
     const rsrc_t rK = make_rsrc(a.Kt + (long)qi * NR, NR * 4u);
     const bool first_ks = (ks == ks0);
     const bool last_ks = (ks == ks1 - 1);
-    if constexpr (ACCREG) static_for<N>([&](auto m) { acc[decltype(m)::value] = c64{0.0f, 0.0f}; });
     for (int j = 0; j < a.nb; ++j) {
+      // the FP32 band sum runs over at most kBandFlush bands before it is folded
+      // into the FP64 sum (every kBandFlush-th band and the last band of each k')
+      const bool group_start = j % kBandFlush == 0;
+      if constexpr (ACCREG) {
+        if (group_start) static_for<N>([&](auto m) { acc[decltype(m)::value] = c64{0.0f, 0.0f}; });
+      }
       hook((ks - ks0) * a.nb + j);
       const rsrc_t rP = make_rsrc(a.P + ((long)ks * a.nb + j) * NR, FB64);
       const rsrc_t rM = make_rsrc(a.M + ((long)ks * a.nb + j) * NR, FB64);
@@ -309,6 +318,9 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
       fft<N, +1>(v);
 
       const bool last_j = (j == a.nb - 1);
+      const bool flush = last_j || (j + 1) % kBandFlush == 0;
+      const bool first_fl = first_ks && j < kBandFlush;  // this target's first fold into FP64
+      const bool last_fl = last_ks && last_j;            // and its last
       if constexpr (ACCREG) {
         static_assert(N % grp_m<N>() == 0, "multiplier groups must tile the line");
         static_for<N / grp_m<N>()>([&](auto cc) {
@@ -340,17 +352,17 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
         };
         using T = std::true_type;
         using F = std::false_type;
-        if (j == 0) {
-          if (last_j) mac(F{}, F{});
+        if (group_start) {
+          if (flush) mac(F{}, F{});
           else mac(F{}, T{});
         } else {
-          if (last_j) mac(T{}, F{});
+          if (flush) mac(T{}, F{});
           else mac(T{}, T{});
         }
       }
-      if (last_j) {
+      if (flush) {
 #pragma clang fp contract(off)
-        // fold the FP32 band sum of this k' into the FP64 running sum
+        // fold the FP32 band sum into the FP64 running sum
         if constexpr (flush_depth<N>() == 0) {
 #pragma unroll
           for (int m1 = 0; m1 < N; ++m1) {
@@ -358,19 +370,19 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
             const double xr = a.scale * (double)v[m1].re;
             const double xi = a.scale * (double)v[m1].im;
             double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
-            if (!first_ks || accumulate) {
+            if (!first_fl || accumulate) {
               const c128 o = ld_c128(rOut, voff_f, so);
               sr = o.re;
               si = o.im;
             }
-            if (!first_ks) {
+            if (!first_fl) {
               const c64 c = ld_c64(rComp, voff_c, so / 2);
               cr = c.re;
               ci = c.im;
             }
             neumaier(sr, cr, xr);
             neumaier(si, ci, xi);
-            if (last_ks) {
+            if (last_fl) {
               st_c128(c128{sr + cr, si + ci}, rOut, voff_f, so);
             } else {
               st_c128(c128{sr, si}, rOut, voff_f, so);
@@ -382,8 +394,8 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
           // every element is loaded and stored unconditionally (the buffers are
           // whole fields) and the uniform flags only select values, so the loop
           // is straight-line code whose loads run ahead of their use
-          const bool use_out = !first_ks || accumulate;
-          const bool use_comp = !first_ks;
+          const bool use_out = !first_fl || accumulate;
+          const bool use_comp = !first_fl;
           constexpr int D = flush_depth<N>();
           c128 oq[D];
           c64 cq[D];
@@ -408,7 +420,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
             neumaier(si, ci, xi);
             // the final value is s + c; before it, s and the compensation (a
             // rounding-error term ~1e-16 |s|, which FP32 keeps)
-            st_c128(last_ks ? c128{sr + cr, si + ci} : c128{sr, si}, rOut, voff_f, so);
+            st_c128(last_fl ? c128{sr + cr, si + ci} : c128{sr, si}, rOut, voff_f, so);
             st_c64(c64{(float)cr, (float)ci}, rComp, voff_c, so / 2);
           });
         }
@@ -447,6 +459,7 @@ __global__ void __launch_bounds__(N * N) __attribute__((amdgpu_waves_per_eu(WPE)
 fused_lockstep_kernel(FusedArgs a, int* counters) {
   __shared__ c64 lds[fused_lds_elems<N>()];
   __shared__ LockstepState st;
+  if (a.gate && *a.gate == 0) return;  // a fallback whose primary launch completed
   const int G = gridDim.x, W = G / 8;
   const int x = blockIdx.x % 8, rank = x * W + blockIdx.x / 8;
   if (threadIdx.x == 0) {
@@ -469,7 +482,9 @@ fused_lockstep_kernel(FusedArgs a, int* counters) {
 }
 
 // out[i] += sum_{p < nparts} parts[p][i], in that order
-__global__ void add_parts_kernel(c128* __restrict__ out, const c128* __restrict__ parts, int nparts, long count) {
+__global__ void add_parts_kernel(c128* __restrict__ out, const c128* __restrict__ parts, int nparts, long count,
+                                 const int* gate) {
+  if (gate && *gate == 0) return;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
     c128 v = out[i];
     for (int p = 0; p < nparts; ++p) {
@@ -557,7 +572,8 @@ hipError_t launch_lockstep_n(const FusedArgs& a, const LockstepCfg& ls, hipStrea
   const long count = (long)a.nitems * N * N * N;
   long g = (count + 255) / 256;
   if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(add_parts_kernel, dim3((unsigned)g), dim3(256), 0, st, a.out, a.part_out, a.ksplit - 1, count);
+  hipLaunchKernelGGL(add_parts_kernel, dim3((unsigned)g), dim3(256), 0, st, a.out, a.part_out, a.ksplit - 1, count,
+                     a.gate);
   return hipGetLastError();
 }
 
@@ -570,13 +586,14 @@ size_t fused_acc_scratch_elems(int n, int nslots) {
   }
 }
 
-int fused_variants(int n) { return (n == 16 || n == 20 || n == 32) ? 2 : 1; }
+// 32^3: 0 the grid form, 1 the lockstep form, 2 the split form (split32.hip),
+// which the caller launches itself
+int fused_variants(int n) { return n == 32 ? 3 : ((n == 16 || n == 20) ? 2 : 1); }
 
 bool fused_has_lockstep(int n) { return n == 32; }
 
-// without a tuned choice: the lockstep form where it exists (measured faster at
-// 32^3: 2.27 s against 2.63 s per application of 11,943,936 pairs)
-int fused_default_variant(int n) { return n == 32 ? 1 : 0; }
+// without a tuned choice at 32^3: the split form
+int fused_default_variant(int n) { return n == 32 ? 2 : 0; }
 
 hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int variant, const LockstepCfg* ls) {
   switch (n) {

@@ -57,6 +57,9 @@ struct FusedArgs {
   // part_out[p-1][t] (t < nitems, item0 = 0), and comp holds ksplit fields per target
   int ksplit;
   c128* part_out;
+  // when not NULL, the lockstep form (and its part combine) runs only if *gate != 0:
+  // the fallback of the split 32^3 kernel, launched behind it on the same stream
+  const int* gate;
 };
 // Persistent lockstep form of the fused kernel, for grid lengths whose FP32
 // partial sums live in global memory: nwg workgroups (a multiple of 8, at most
@@ -77,6 +80,28 @@ hipError_t launch_fused_apply(int n, const FusedArgs& a, hipStream_t st, int var
                               const LockstepCfg* ls = nullptr);
 int fused_variants(int n);
 size_t fused_acc_scratch_elems(int n, int nslots);  // c64 elements needed in accs (0 if registers)
+
+// Split 32^3 form (split32.hip): each target on two workgroups of one XCD,
+// nwg workgroups (a multiple of 16, at most one per CU), accumulate = 0 only.
+// On a timed-out rendezvous or an XCD mismatch the launch stops and leaves
+// status[0] != 0; the caller then runs the lockstep form gated on status.
+struct SplitArgs {
+  FusedArgs f;          // X, P, M, qidx, out, comp, nk, nx, nb, nitems, scale (accumulate must be 0)
+  const float* SD;      // [nq][16384][2]: (S, D) = K(l1') +- K(l1' + 16) at (l2 * 512 + 32 l1' + l3), 1/N_r folded
+  c64* xbuf;            // [nwg/2 pairs][2 halves][2 buffers][16384] exchange buffers
+  int* flags;           // split32_flag_ints(nwg) ints: rendezvous counters, then XCD ids
+  int* status;          // [0] abort word, cleared by the launch
+  int band_flush;       // bands per FP32 partial sum (>= 1)
+  long wait_ticks;      // bound of one rendezvous wait (100 MHz ticks); < 0 stops the launch at once
+};
+size_t split32_flag_ints(int nwg);
+size_t split32_xbuf_elems(int nwg);   // c64 elements
+size_t split32_sd_floats(int nq);
+hipError_t launch_build_sd32(float* SD, const double* K, int nq, hipStream_t st);
+hipError_t launch_split32(const SplitArgs& s, int nwg, hipStream_t st);
+// count[0] += (status[0] != 0); p[0] = 0 (diagnostics of the split form's fallbacks)
+hipError_t launch_count_abort(long long* count, const int* status, hipStream_t st);
+hipError_t launch_zero_ll(long long* p, hipStream_t st);
 
 // ---- fused FP64 form -------------------------------------------------------
 struct Fused64Args {

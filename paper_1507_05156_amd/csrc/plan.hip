@@ -140,6 +140,13 @@ fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
     if ((e = launch_build_table_fused((float*)c.Kt.ptr, (const double*)c.K64.ptr, c.nq, c.geom.n1, 0)) !=
         hipSuccess)
       return hip_fail(e, "FP32 kernel table");
+    if (c.geom.n1 == 32) {
+      // (S, D) pairs of the split 32^3 form
+      if ((s = c.SD.ensure(split32_sd_floats(c.nq) * sizeof(float), 0, "split-form kernel tables")) != FOCK_OK)
+        return s;
+      if ((e = launch_build_sd32((float*)c.SD.ptr, (const double*)c.K64.ptr, c.nq, 0)) != hipSuccess)
+        return hip_fail(e, "split-form kernel table");
+    }
   }
   if (prec == FOCK_FP64_FUSED && c.geom.n1 == c.geom.n2 && c.geom.n2 == c.geom.n3 && fused64_supported(c.geom.n1)) {
     if ((s = c.Kt64.ensure((size_t)c.nq * c.nr * sizeof(double), 0, "fused FP64 kernel tables")) != FOCK_OK)
@@ -200,12 +207,13 @@ void Plan::destroy() {
     c.qzero.release();
     c.K64.release();
     c.Kt.release();
+    c.SD.release();
     c.Kt64.release();
     c.kvec.release();
   }
   for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &srcbuf, &srcout,
                     &psi0, &phiA, &phiB, &predb, &srcbuf2, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms,
-                    &red6, &vloc_buf, &sync, &parts})
+                    &red6, &vloc_buf, &sync, &parts, &xbuf, &sflags, &sstatus, &fallbacks})
     b->release();
   bstate.release();
   eig.release();

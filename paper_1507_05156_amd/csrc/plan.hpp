@@ -51,6 +51,7 @@ struct Cell {
   DevBuf qidx, qvec, qzero;   // int[nk*nk], double[nq*3], int[nq]
   DevBuf K64;                 // double[nq][nr], 1/N_r folded, natural slot order
   DevBuf Kt;                  // float[nq][nr], fused-kernel layout (FP32 plans)
+  DevBuf SD;                  // float[nq][nr/2][2], (S, D) pairs of the split 32^3 form (FP32 plans, n = 32)
   DevBuf Kt64;                // double[nq][nr], fused FP64 kernel layout (FP64-fused plans)
   bool f64f = false;          // this cell runs the fused FP64 kernel
   DevBuf kvec;                // double[nk][3] k-points on the device
@@ -113,6 +114,10 @@ struct Plan {
   DevBuf psi0, phiA, phiB, predb, srcbuf2, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
   DevBuf sync;                              // lockstep counters of the persistent fused form
   DevBuf parts;                             // FP64 part sums of the lockstep form's k' split
+  DevBuf xbuf, sflags, sstatus;             // exchange buffers, rendezvous counters, abort word of the split form
+  DevBuf fallbacks;                         // split launches that fell back (counted while profiling)
+  int band_flush = 16;                      // bands per FP32 partial sum of the split form (FOCKMI_BAND_FLUSH)
+  long split_wait_ticks = 5000000;          // rendezvous bound of the split form, 50 ms (FOCKMI_SPLIT_WAIT_TICKS)
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 2 doubles for reductions
   bool profiling = false;

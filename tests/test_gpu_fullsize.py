@@ -34,18 +34,44 @@ def row_err(got, ref):
 
 
 def test_bench_workload_fp32_sampled_rows(device):
-    """32^3 / 216 k / 16 bands through the fused FP32 kernel, as bench.py runs it."""
+    """32^3 / 216 k / 16 bands through the fused FP32 kernel, as bench.py runs it (the
+    split form: targets t run on CU pair t mod 128, XCD (t mod 128) / 16, round t / 128;
+    each target's two halves hold the even and odd m1 planes). One sampled row per XCD,
+    spread over the rounds, the first and the last target among them."""
     print("[gpu] full size 32^3 fp32 rows", flush=True)
     from paper_1507_05156_amd.api import Plan
+    from tests.oracle_rows import oracle_rows
     cell, kp, u = synth.workload(2)
     plan = Plan(dict(n=32, a=cell, kpts=kp, nb=16, omega=OMEGA), prec="fp32")
+    plan.profile(True)
     got = plan.apply(to_dev(u)).cpu().numpy()
-    rows = [(0, 0), (215, 15)]
-    ref = oracle.fock_apply(u, u, kp, cell, OMEGA, rows=rows)
+    assert plan.profile_fallbacks() == 0
+    plan.profile(False)
+    targets = [0, 128 * 5 + 16 + 3, 128 * 9 + 32 + 8, 128 * 13 + 48 + 12, 128 * 17 + 64 + 1, 128 * 21 + 80 + 15,
+               128 * 24 + 96 + 6, 3455]
+    rows = [(t // 16, t % 16) for t in targets]
+    ref = oracle_rows(u, kp, cell, OMEGA, rows)
     for k, i in rows:
-        e = row_err(got[k, i], ref[k, i])
+        e = row_err(got[k, i], ref[(k, i)])
         print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
         assert e < 1e-6, (k, i, e)
+
+
+def test_bench_workload_fp32_every_k_vs_fp64(device):
+    """The same application against the plain FP64 GPU path at every one of the 216
+    k-points (the per-k error bench.py reports), and E_x."""
+    print("[gpu] full size 32^3 fp32 vs fp64 at every k", flush=True)
+    from paper_1507_05156_amd.api import Plan
+    cell, kp, u = synth.workload(2)
+    d = to_dev(u)
+    p32 = Plan(dict(n=32, a=cell, kpts=kp, nb=16, omega=OMEGA), prec="fp32")
+    o32 = p32.apply(d)
+    p32.close()
+    p64 = Plan(dict(n=32, a=cell, kpts=kp, nb=16, omega=OMEGA), prec="fp64")
+    o64 = p64.apply(d)
+    rel = ((o32 - o64).reshape(len(kp), -1).norm(dim=1) / o64.reshape(len(kp), -1).norm(dim=1)).cpu().numpy()
+    print(f"  per-k rel err max {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
+    assert rel.max() < 1e-6
 
 
 def test_batched_workload_sampled_rows(device):

@@ -44,10 +44,11 @@ def test_krange_rows_equal_the_full_application(device, prec):
     assert e < (1e-10 if prec != "fp32" else 1e-6), e
 
 
-def test_krange_lockstep_32cube(device):
-    """32^3 lockstep form (its k' split depends on the number of targets, so the FP64
-    additions may group differently): rows agree to rounding and with the oracle."""
-    print("[gpu] krange 32^3 lockstep", flush=True)
+def test_krange_32cube(device):
+    """32^3 default form (the split form: each target's sum is independent of the
+    target count, so the rows are bitwise equal; the lockstep form's k' split may group
+    its FP64 additions differently): rows agree to rounding and with the oracle."""
+    print("[gpu] krange 32^3", flush=True)
     cell = synth.cubic_cell()
     kp = synth.gamma_mesh(2, cell)
     u = synth.orbitals(32, cell, kp, 2, seed=403)

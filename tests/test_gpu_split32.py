@@ -1,0 +1,104 @@
+"""The split 32^3 form of the FP32 fused kernel (each target on two CUs of one XCD,
+one exchange per pair) through the C ABI: against the FP64 oracle, bitwise
+repeatability, more bands than one FP32 partial sum holds (two folds per k'), a
+target count that leaves most CU pairs idle, and its fallback (the host forces
+every rendezvous to stop; the lockstep form behind it then gives the result)."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1507_05156_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+OMEGA = synth.OMEGA_HSE
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def rel_per_k(got, ref):
+    return max(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k]) for k in range(ref.shape[0]))
+
+
+def plan32(kp, nb, cell, **env):
+    from paper_1507_05156_amd.api import Plan
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return Plan(dict(n=32, a=cell, kpts=kp, nb=nb, omega=OMEGA), prec="fp32")
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("mesh,nb", [((2, 1, 1), 3), ((1, 1, 1), 20)])
+def test_split_matches_oracle(device, mesh, nb):
+    print(f"[gpu] split 32^3 mesh={mesh} nb={nb}", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(mesh[0], cell, mesh[1], mesh[2])
+    u = synth.orbitals(32, cell, kp, nb, seed=800 + nb)
+    plan = plan32(kp, nb, cell)
+    plan.profile(True)
+    d = to_dev(u)
+    got = plan.apply(d).cpu().numpy()
+    again = plan.apply(d).cpu().numpy()
+    assert plan.profile_fallbacks() == 0       # the split launches ran to completion
+    plan.profile(False)
+    assert np.array_equal(got, again)          # bitwise repeatable
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    e = rel_per_k(got, ref)
+    print(f"  per-k rel err {e:.3e}", flush=True)
+    assert e < 1e-6
+
+
+def test_split_fallback_when_forced(device):
+    """FOCKMI_SPLIT_WAIT_TICKS < 0 makes every rendezvous stop at once: the launch sets its
+    abort word and the lockstep form behind it computes the whole application."""
+    print("[gpu] split 32^3 forced fallback", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(32, cell, kp, 3, seed=810)
+    plan = plan32(kp, 3, cell, FOCKMI_SPLIT_WAIT_TICKS=-1)
+    plan.profile(True)
+    got = plan.apply(to_dev(u)).cpu().numpy()
+    assert plan.profile_fallbacks() == 1
+    plan.profile(False)
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    assert rel_per_k(got, ref) < 1e-6
+
+
+def test_split_several_rounds_phi_and_shard(device):
+    """27 k x 10 bands = 270 targets on 128 CU pairs (two full rounds and a partial
+    one); separate targets phi (3 per k); one k-range shard, bitwise equal to the full
+    application's rows (each target's sum does not depend on the CU pair that runs it)."""
+    print("[gpu] split 32^3 rounds, phi, shard", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(3, cell)
+    u = synth.orbitals(32, cell, kp, 10, seed=820)
+    plan = plan32(kp, 10, cell)
+    plan.profile(True)
+    d = to_dev(u)
+    full = plan.apply(d).cpu().numpy()
+    rows = [(0, 0), (12, 7), (26, 9)]
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA, rows=rows)
+    for k, i in rows:
+        e = np.linalg.norm(full[k, i] - ref[k, i]) / np.linalg.norm(ref[k, i])
+        print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
+        assert e < 1e-6
+    part = plan.apply_krange(d, 12, 5).cpu().numpy()
+    assert np.array_equal(part, full[12:17])
+    phi = synth.random_fields((len(kp), 3, 32, 32, 32), seed=821)
+    got = plan.apply(d, to_dev(phi)).cpu().numpy()
+    ref = oracle.fock_apply(u, phi, kp, cell, OMEGA, rows=[(20, 2)])
+    assert np.linalg.norm(got[20, 2] - ref[20, 2]) / np.linalg.norm(ref[20, 2]) < 1e-6
+    assert plan.profile_fallbacks() == 0
+    plan.profile(False)

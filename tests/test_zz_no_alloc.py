@@ -77,8 +77,8 @@ def test_noalloc_32cube_cell(device):
     d = to_dev(u)
     st, got = noalloc(plan, d, d)
     assert st == N.FOCK_OK, N.lib().fock_last_error()
-    ref = plan.apply(d)
-    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-12
+    ref = plan.apply(d)  # the split form: the same sum in other FP32 roundings
+    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
     assert rel(got.cpu().numpy(), oracle.fock_apply(u, u, kp, cell, OMEGA)) < 1e-6
 
 
