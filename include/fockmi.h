@@ -114,7 +114,8 @@ fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void
 fock_status fock_apply_krange(fockmi_plan plan, int cell, const void* u_occ, int k0, int nk_out, const void* phi,
                               int nphi, void* vphi, void* stream);
 
-/* Exchange energy of u_occ (the E_xc piece of Eq. (22)) in FP64:
+/* Exchange energy of u_occ (the E_xc piece of Eq. (22)) in FP64 (the final
+ * reduction in double-double, rounded once):
  *   *ex_re, *ex_im <- E_x (the imaginary part is a check, zero in exact arithmetic).
  * Host pointers; synchronises the stream. Either output pointer may be NULL. */
 fock_status fock_energy(fockmi_plan plan, int cell, const void* u_occ, double* ex_re, double* ex_im,
@@ -190,6 +191,18 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
  * Synchronises the stream. */
 fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],
                           double alpha, double* e_out, void* grad_psi, double grad_a[3], void* stream);
+
+/* Excitation energy of Eq. (22) with E_GS replaced by the energy of the initial
+ * state (E_ex = E[psi_t; A_t/c] - E[psi_0; A_0/c], both as taylor_energy). Both
+ * energies (about 86 Ha for the 24^3 / 64 k / 16-band differentiation workload)
+ * are reduced in double-double and subtracted before the one final rounding, so
+ * E_ex carries FP64 relative precision of its own instead of one unit in the last
+ * place of E; central differences of E_ex at small steps rely on that.
+ *   psi_t, psi_0 : device [nk][nb][N_r] complex128;  A_t, A_0 : host [3]
+ *   *e_ex (host) <- E_ex.  Synchronises the stream. Not available for a down-sampled cell. */
+fock_status taylor_excitation_energy(fockmi_plan plan, int cell, const void* psi_t, const double A_t[3],
+                                     const void* psi_0, const double A_0[3], const double* vloc, double alpha,
+                                     double* e_ex, void* stream);
 
 /* Reverse mode of taylor_energy for the cotangent g_e of E (same arguments):
  *   g_psi (device, may be NULL) <- g_e dE/dpsi = 2 g_e (g_s/N_k)(Omega/N_r) (T + v_loc + alpha V_x[psi]) psi

@@ -28,7 +28,7 @@ FOCK_FP32_COMP = 1
 FOCK_FP64_FUSED = 2
 
 EXPORTS = ["fock_plan_create", "fock_plan_destroy", "fock_apply", "fock_apply_krange", "fock_energy", "fock_energy_vjp",
-           "fock_vjp", "taylor_step", "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "taylor_energy_vjp",
+           "fock_vjp", "taylor_step", "taylor_step_pc", "taylor_step_vjp", "taylor_energy", "taylor_energy_vjp", "taylor_excitation_energy",
            "taylor_current", "fock_orthonormalize", "fock_eigensolve",
            "fock_excited_density", "fock_apply_batched", "fock_apply_noalloc", "fock_profile_enable", "fock_profile_fallbacks",
            "fock_profile_read", "fock_last_error"]
@@ -72,6 +72,7 @@ def lib():
     L.taylor_energy.argtypes = [vp, i, vp, vp, pd, d, pd, vp, pd, vp]
     L.taylor_energy_vjp.argtypes = [vp, i, vp, vp, pd, d, d, vp, pd, vp]
     L.taylor_current.argtypes = [vp, i, vp, pd, pd, vp]
+    L.taylor_excitation_energy.argtypes = [vp, i, vp, pd, vp, pd, vp, d, pd, vp]
     L.fock_orthonormalize.argtypes = [vp, i, vp, vp]
     L.fock_eigensolve.argtypes = [vp, i, vp, vp, pd, d, vp, d, i, pd, pd, C.POINTER(i), vp]
     L.fock_excited_density.argtypes = [vp, i, vp, vp, pd, vp]

@@ -231,6 +231,19 @@ class Plan:
                                         float(alpha), C.byref(e), _ptr(g), ga if want_grad else None, _stream()))
         return (e.value, g, np.array([ga[0], ga[1], ga[2]])) if want_grad else e.value
 
+    def excitation_energy(self, psi_t, a_t, psi_0, a_0, alpha, vloc=None, cell=0):
+        """E[psi_t; a_t] - E[psi_0; a_0], both reduced and subtracted in double-double."""
+        c = self.cells[cell]
+        self._check(psi_t, cell, c["nb"], "psi_t")
+        self._check(psi_0, cell, c["nb"], "psi_0")
+        at = (C.c_double * 3)(*[float(x) for x in a_t])
+        a0 = (C.c_double * 3)(*[float(x) for x in a_0])
+        e = C.c_double()
+        N.check(self._lib.taylor_excitation_energy(self._h, cell, _ptr(psi_t), at, _ptr(psi_0), a0,
+                                                   _ptr(vloc) if vloc is not None else None, float(alpha),
+                                                   C.byref(e), _stream()))
+        return e.value
+
     def energy_functional_vjp(self, psi, a_over_c, alpha, g_e=1.0, vloc=None, cell=0):
         """(g_e dE/dpsi, g_e dE/d(A/c)) of the energy functional for its cotangent g_e."""
         c = self.cells[cell]

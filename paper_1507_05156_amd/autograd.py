@@ -4,6 +4,7 @@
   FockEnergy         E_x[u]                            backward: fock_energy_vjp
   TaylorStep         psi(t+dt) = T4(-i dt h) psi(t)    backward: taylor_step_vjp
   EnergyFunctional   E[psi; A/c]                       backward: taylor_energy_vjp
+  ExcitationEnergy   E[psi_t; a_t] - E[psi_0; a_0]     forward: taylor_excitation_energy
   propagate          N Taylor steps under the sin^2 pulse of Eq. (21), checkpointed every
                      `checkpoint_every` steps, returning psi(t_N) and E_ex = E(t_N) - E(t_0)
 
@@ -88,6 +89,30 @@ class EnergyFunctional(torch.autograd.Function):
         return gpsi, torch.tensor(ga, dtype=torch.float64), None, None, None, None
 
 
+class ExcitationEnergy(torch.autograd.Function):
+    """E_ex = E[psi_t; a_t] - E[psi_0; a_0] (taylor_excitation_energy: double-double
+    reductions, one final rounding); backward: taylor_energy_vjp with +g and -g."""
+
+    @staticmethod
+    def forward(ctx, psi_t, a_t, psi_0, a_0, plan: Plan, alpha: float, vloc=None, cell: int = 0):
+        ctx.plan, ctx.alpha, ctx.vloc, ctx.cell = plan, alpha, vloc, cell
+        ctx.at = [float(x) for x in a_t.detach().cpu().reshape(3)]
+        ctx.a0 = [float(x) for x in a_0.detach().cpu().reshape(3)]
+        ctx.save_for_backward(psi_t, psi_0)
+        e = plan.excitation_energy(psi_t.contiguous(), ctx.at, psi_0.contiguous(), ctx.a0, alpha, vloc=vloc, cell=cell)
+        return torch.tensor(e, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        psi_t, psi_0 = ctx.saved_tensors
+        gt, gat = ctx.plan.energy_functional_vjp(psi_t.contiguous(), ctx.at, ctx.alpha, float(g), vloc=ctx.vloc,
+                                                 cell=ctx.cell)
+        g0, ga0 = ctx.plan.energy_functional_vjp(psi_0.contiguous(), ctx.a0, ctx.alpha, -float(g), vloc=ctx.vloc,
+                                                 cell=ctx.cell)
+        return (gt, torch.tensor(gat, dtype=torch.float64), g0, torch.tensor(ga0, dtype=torch.float64),
+                None, None, None, None)
+
+
 def fock_apply(u, phi, plan, cell=0):
     return FockApply.apply(u, phi, plan, cell)
 
@@ -128,6 +153,6 @@ def propagate(plan, psi0, A0, nsteps=20, dt=0.02, alpha=0.25, omega_l=0.0569614,
             psi = torch.utils.checkpoint.checkpoint(segment, psi, A0, s0, s1, use_reentrant=False)
         else:
             psi = segment(psi, A0, s0, s1)
-    eN = EnergyFunctional.apply(psi, pulse_a_over_c(nsteps * dt, A0, omega_l, Td, direction), plan, alpha, vloc, cell)
-    e0 = EnergyFunctional.apply(psi0, pulse_a_over_c(0.0, A0, omega_l, Td, direction), plan, alpha, vloc, cell)
-    return psi, eN - e0
+    e_ex = ExcitationEnergy.apply(psi, pulse_a_over_c(nsteps * dt, A0, omega_l, Td, direction), psi0,
+                                  pulse_a_over_c(0.0, A0, omega_l, Td, direction), plan, alpha, vloc, cell)
+    return psi, e_ex

@@ -143,7 +143,8 @@ hipError_t launch_fused_batched(const BatchArgs& b, int nthreads, int nwg, hipSt
 
 // ---- helpers ---------------------------------------------------------------
 hipError_t launch_to_c64(c64* dst, const c128* src, long count, hipStream_t st);
-// partial[b] for b < nblk, then dst[0..1] = sum conj(a) b (re, im), fixed order
+// partial[4b..4b+3] for b < nblk, then dst[0..3] = sum conj(a) b as double-double
+// (re.hi, re.lo, im.hi, im.lo), fixed order
 hipError_t launch_dot(double* dst, double* partial, int nblk, const c128* a, const c128* b, long count,
                       hipStream_t st);
 hipError_t launch_scale_add(c128* y, const c128* x, double sre, double sim, long count, hipStream_t st);

@@ -1,4 +1,4 @@
-// Small FP64 helpers: complex64 shadows, a deterministic inner product, axpy.
+// Small FP64 helpers: complex64 shadows, a deterministic double-double inner product, axpy.
 #include "kernels.hpp"
 
 namespace fockmi {
@@ -14,54 +14,90 @@ __global__ void to_c64_kernel(c64* __restrict__ dst, const c128* __restrict__ sr
 
 constexpr int kDotThreads = 256;
 
-// partial[b] = sum over a fixed grid-stride slice of conj(a) * b, tree-reduced in a fixed order
+// Double-double accumulation (hi + lo, |lo| <= ulp(hi)/2): x is added to hi with an
+// error-free two-sum whose rounding error goes into lo. Products enter with their
+// exact rounding error from an FMA, so the sums are accurate to a few units of
+// 2^-104 relative: a difference of two nearby energies keeps its digits.
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ void dd_add(dd& a, double x) {
+#pragma clang fp contract(off)
+  const double s = a.hi + x;
+  const double bb = s - a.hi;
+  const double err = (a.hi - (s - bb)) + (x - bb);
+  a.hi = s;
+  a.lo += err;
+}
+__device__ __forceinline__ void dd_add(dd& a, dd b) {
+#pragma clang fp contract(off)
+  dd_add(a, b.hi);
+  a.lo += b.lo;
+}
+// a += x * y, exactly up to the final rounding of the two parts
+__device__ __forceinline__ void dd_add_prod(dd& a, double x, double y) {
+#pragma clang fp contract(off)
+  const double p = x * y;
+  const double e = fma(x, y, -p);
+  dd_add(a, p);
+  a.lo += e;
+}
+
+// partial[4 b .. 4 b + 3] = (re.hi, re.lo, im.hi, im.lo) of sum conj(a) b over a fixed
+// grid-stride slice, tree-reduced in a fixed order
 __global__ void __launch_bounds__(kDotThreads) dot_partial_kernel(double* __restrict__ partial,
                                                                   const c128* __restrict__ a,
                                                                   const c128* __restrict__ b, long count) {
-  __shared__ double sre[kDotThreads], sim[kDotThreads];
-  double re = 0.0, im = 0.0;
+  __shared__ dd sre[kDotThreads], sim[kDotThreads];
+  dd re{0.0, 0.0}, im{0.0, 0.0};
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
     const c128 x = a[i], y = b[i];
-    re += x.re * y.re + x.im * y.im;
-    im += x.re * y.im - x.im * y.re;
+    dd_add_prod(re, x.re, y.re);
+    dd_add_prod(re, x.im, y.im);
+    dd_add_prod(im, x.re, y.im);
+    dd_add_prod(im, -x.im, y.re);
   }
   sre[threadIdx.x] = re;
   sim[threadIdx.x] = im;
   __syncthreads();
   for (int w = kDotThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      sre[threadIdx.x] += sre[threadIdx.x + w];
-      sim[threadIdx.x] += sim[threadIdx.x + w];
+      dd_add(sre[threadIdx.x], sre[threadIdx.x + w]);
+      dd_add(sim[threadIdx.x], sim[threadIdx.x + w]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = sre[0];
-    partial[2 * blockIdx.x + 1] = sim[0];
+    partial[4 * blockIdx.x + 0] = sre[0].hi;
+    partial[4 * blockIdx.x + 1] = sre[0].lo;
+    partial[4 * blockIdx.x + 2] = sim[0].hi;
+    partial[4 * blockIdx.x + 3] = sim[0].lo;
   }
 }
 
 __global__ void __launch_bounds__(kDotThreads) dot_final_kernel(double* __restrict__ dst,
                                                                 const double* __restrict__ partial, int nblk) {
-  __shared__ double sre[kDotThreads], sim[kDotThreads];
-  double re = 0.0, im = 0.0;
+  __shared__ dd sre[kDotThreads], sim[kDotThreads];
+  dd re{0.0, 0.0}, im{0.0, 0.0};
   for (int i = threadIdx.x; i < nblk; i += kDotThreads) {
-    re += partial[2 * i];
-    im += partial[2 * i + 1];
+    dd_add(re, dd{partial[4 * i + 0], partial[4 * i + 1]});
+    dd_add(im, dd{partial[4 * i + 2], partial[4 * i + 3]});
   }
   sre[threadIdx.x] = re;
   sim[threadIdx.x] = im;
   __syncthreads();
   for (int w = kDotThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      sre[threadIdx.x] += sre[threadIdx.x + w];
-      sim[threadIdx.x] += sim[threadIdx.x + w];
+      dd_add(sre[threadIdx.x], sre[threadIdx.x + w]);
+      dd_add(sim[threadIdx.x], sim[threadIdx.x + w]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    dst[0] = sre[0];
-    dst[1] = sim[0];
+    dst[0] = sre[0].hi;
+    dst[1] = sre[0].lo;
+    dst[2] = sim[0].hi;
+    dst[3] = sim[0].lo;
   }
 }
 

@@ -223,22 +223,30 @@ void Plan::destroy() {
 }
 
 fock_status Plan::dot(const c128* a, const c128* b, size_t count, hipStream_t st, double* re, double* im) {
+  double r[4];
+  fock_status s = dot_dd(a, b, count, st, r);
+  if (s != FOCK_OK) return s;
+  *re = r[0] + r[1];
+  *im = r[2] + r[3];
+  return FOCK_OK;
+}
+
+fock_status Plan::dot_dd(const c128* a, const c128* b, size_t count, hipStream_t st, double out[4]) {
   const int nblk = 1024;
   fock_status s;
-  if ((s = partial.ensure(2 * nblk * sizeof(double), 0, "reduction partials")) != FOCK_OK) return s;
-  if ((s = dotres.ensure(2 * sizeof(double), 0, "reduction result")) != FOCK_OK) return s;
+  if ((s = partial.ensure(4 * nblk * sizeof(double), 0, "reduction partials")) != FOCK_OK) return s;
+  if ((s = dotres.ensure(4 * sizeof(double), 0, "reduction result")) != FOCK_OK) return s;
   hipError_t e;
   if (!host_pinned) {
-    if ((e = hipHostMalloc((void**)&host_pinned, 2 * sizeof(double), 0)) != hipSuccess)
+    if ((e = hipHostMalloc((void**)&host_pinned, 4 * sizeof(double), 0)) != hipSuccess)
       return hip_fail(e, "pinned host buffer");
   }
   if ((e = launch_dot((double*)dotres.ptr, (double*)partial.ptr, nblk, a, b, (long)count, st)) != hipSuccess)
     return hip_fail(e, "reduction");
-  if ((e = hipMemcpyAsync(host_pinned, dotres.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+  if ((e = hipMemcpyAsync(host_pinned, dotres.ptr, 4 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return hip_fail(e, "reduction copy");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "reduction sync");
-  *re = host_pinned[0];
-  *im = host_pinned[1];
+  for (int i = 0; i < 4; ++i) out[i] = host_pinned[i];
   return FOCK_OK;
 }
 

@@ -119,7 +119,7 @@ struct Plan {
   int band_flush = 16;                      // bands per FP32 partial sum of the split form (FOCKMI_BAND_FLUSH)
   long split_wait_ticks = 5000000;          // rendezvous bound of the split form, 50 ms (FOCKMI_SPLIT_WAIT_TICKS)
   std::vector<double> host_norms;
-  double* host_pinned = nullptr;            // 2 doubles for reductions
+  double* host_pinned = nullptr;            // 4 doubles for reductions
   bool profiling = false;
   // autotuning: the cache is read at plan creation when a path is given; missing
   // keys are measured on first use and the file is rewritten
@@ -163,6 +163,8 @@ struct Plan {
                      const c64** out);
   // sum conj(a) b over count elements in FP64 (fixed order); synchronises st
   fock_status dot(const c128* a, const c128* b, size_t count, hipStream_t st, double* re, double* im);
+  // the same sum as double-double: out = (re.hi, re.lo, im.hi, im.lo)
+  fock_status dot_dd(const c128* a, const c128* b, size_t count, hipStream_t st, double out[4]);
 
   // propagator pieces (prop_api.hip)
   fock_status kinetic(Cell& c, const c128* x, int nf, c128* y, const double a[3], hipStream_t st);

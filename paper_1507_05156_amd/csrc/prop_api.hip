@@ -271,11 +271,34 @@ fock_status taylor_step_vjp(fockmi_plan plan, int cell, const void* psi_n, const
 
 namespace {
 
+// double-double values on the host (hi + lo), for energies whose differences are
+// taken: the two-sum keeps the rounding error of every addition
+struct hdd {
+  double hi, lo;
+};
+hdd two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+hdd dd_add(hdd a, hdd b) {
+#pragma clang fp contract(off)
+  hdd s = two_sum(a.hi, b.hi);
+  return two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+hdd dd_scale(hdd a, double c) {
+#pragma clang fp contract(off)
+  const double p = a.hi * c;
+  const double e = std::fma(a.hi, c, -p) + a.lo * c;
+  return two_sum(p, e);
+}
+
 // E = (g_s/N_k)(Omega/N_r) sum conj(psi) (T[a] + v_loc) psi + alpha E_x[psi] (into *e_out when
 // given), and the gradients times the cotangent g_e: grad_psi <- g_e dE/dpsi (PyTorch
 // convention, 2 (g_s/N_k)(Omega/N_r) (T + v_loc + alpha V_x[psi]) psi) and grad_a <- g_e dE/d(A/c).
 fock_status energy_impl(Plan* p, Cell& c, const void* psi, const double* vloc, const double A_over_c[3], double alpha,
-                        double g_e, double* e_out, void* grad_psi, double grad_a[3], hipStream_t st) {
+                        double g_e, hdd* e_out, void* grad_psi, double grad_a[3], hipStream_t st) {
   if (c.ds) return fail(FOCK_ERR_ARG, "the energy functional is not available for a down-sampled cell");
   if (!psi || !A_over_c) return fail(FOCK_ERR_ARG, "NULL pointer");
   if (!aligned16(psi) || (grad_psi && !aligned16(grad_psi))) return fail(FOCK_ERR_ARG, "misaligned pointer");
@@ -293,11 +316,13 @@ fock_status energy_impl(Plan* p, Cell& c, const void* psi, const double* vloc, c
     c128* hpsi = (c128*)p->lam.ptr;
     if ((s = p->h_apply(c, P, nullptr, P, hpsi, nullptr, 1.0, 0.0, vloc, A_over_c, alpha, st)) != FOCK_OK) return s;
     if (e_out) {
-      double hre, him, xre = 0.0, xim = 0.0;
-      if ((s = p->dot(P, hpsi, count, st, &hre, &him)) != FOCK_OK) return s;
-      if (alpha != 0.0 && (s = p->dot(P, (const c128*)p->vxb.ptr, count, st, &xre, &xim)) != FOCK_OK) return s;
-      // sum conj(psi) h psi counts V_x with alpha; the energy counts it with alpha / 2
-      *e_out = w * (hre - 0.5 * alpha * xre);
+      // in double-double: sum conj(psi) h psi counts V_x with alpha, the energy
+      // counts it with alpha / 2
+      double h4[4], x4[4] = {0.0, 0.0, 0.0, 0.0};
+      if ((s = p->dot_dd(P, hpsi, count, st, h4)) != FOCK_OK) return s;
+      if (alpha != 0.0 && (s = p->dot_dd(P, (const c128*)p->vxb.ptr, count, st, x4)) != FOCK_OK) return s;
+      const hdd hx = dd_add(two_sum(h4[0], h4[1]), dd_scale(two_sum(x4[0], x4[1]), -0.5 * alpha));
+      *e_out = dd_scale(hx, w);
     }
     if (grad_psi) {
       if ((e = launch_zero((c128*)grad_psi, count, st)) != hipSuccess) return hip_fail(e, "zero");
@@ -335,7 +360,29 @@ fock_status taylor_energy(fockmi_plan plan, int cell, const void* psi, const dou
   fock_status s = common_checks(plan, cell, &p);
   if (s != FOCK_OK) return s;
   if (!e_out) return fail(FOCK_ERR_ARG, "e_out is NULL");
-  return energy_impl(p, p->cells[cell], psi, vloc, A_over_c, alpha, 1.0, e_out, grad_psi, grad_a, (hipStream_t)stream);
+  hdd e{0.0, 0.0};
+  s = energy_impl(p, p->cells[cell], psi, vloc, A_over_c, alpha, 1.0, &e, grad_psi, grad_a, (hipStream_t)stream);
+  *e_out = e.hi + e.lo;
+  return s;
+}
+
+fock_status taylor_excitation_energy(fockmi_plan plan, int cell, const void* psi_t, const double A_t[3],
+                                     const void* psi_0, const double A_0[3], const double* vloc, double alpha,
+                                     double* e_ex, void* stream) {
+  Plan* p = nullptr;
+  fock_status s = common_checks(plan, cell, &p);
+  if (s != FOCK_OK) return s;
+  if (!e_ex) return fail(FOCK_ERR_ARG, "e_ex is NULL");
+  hdd et{0.0, 0.0}, e0{0.0, 0.0};
+  if ((s = energy_impl(p, p->cells[cell], psi_t, vloc, A_t, alpha, 1.0, &et, nullptr, nullptr, (hipStream_t)stream)) !=
+      FOCK_OK)
+    return s;
+  if ((s = energy_impl(p, p->cells[cell], psi_0, vloc, A_0, alpha, 1.0, &e0, nullptr, nullptr, (hipStream_t)stream)) !=
+      FOCK_OK)
+    return s;
+  const hdd d = dd_add(et, hdd{-e0.hi, -e0.lo});
+  *e_ex = d.hi + d.lo;
+  return FOCK_OK;
 }
 
 fock_status taylor_energy_vjp(fockmi_plan plan, int cell, const void* psi, const double* vloc, const double A_over_c[3],

@@ -99,3 +99,24 @@ def test_kpoints_differing_by_a_reciprocal_vector(device, prec):
     assert np.all(np.isfinite(got))
     ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
     assert rel(got, ref) < TOL[prec]
+
+
+def test_excitation_energy_double_double(device):
+    """taylor_excitation_energy against the oracle's energy functional at both states,
+    and its cancellation: the same state twice gives exactly 0, a state against itself
+    with a phase gives 0 to rounding."""
+    print("[gpu] excitation energy", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(16, cell, kp, 2, seed=615)
+    w = synth.orbitals(16, cell, kp, 2, seed=616)
+    vloc = np.random.default_rng(617).standard_normal((16, 16, 16)) * 0.05
+    at, a0 = np.array([0.0, 0.0, 0.04]), np.array([0.01, 0.0, 0.0])
+    plan = plan_for(cell, kp, 2, 16, "fp64")
+    e = plan.excitation_energy(to_dev(w), at, to_dev(u), a0, 0.25, vloc=to_dev(vloc))
+    ref = otaylor.energy_matfree(w, kp, cell, OMEGA, at, 0.25, vloc)[0] - \
+        otaylor.energy_matfree(u, kp, cell, OMEGA, a0, 0.25, vloc)[0]
+    assert abs(e - ref) < 1e-11 * abs(otaylor.energy_matfree(u, kp, cell, OMEGA, a0, 0.25, vloc)[0])
+    assert plan.excitation_energy(to_dev(u), a0, to_dev(u), a0, 0.25) == 0.0
+    z = plan.excitation_energy(to_dev(u * np.exp(0.3j)), a0, to_dev(u), a0, 0.25)
+    assert abs(z) < 1e-14
