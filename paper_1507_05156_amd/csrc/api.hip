@@ -17,6 +17,7 @@
 #include <tuple>
 #include <vector>
 #include <cstdlib>
+#include <cstdint>
 
 #include "../../include/fockmi.h"
 #include "kernels.hpp"
@@ -93,8 +94,8 @@ fock_status Plan::run_plain(Cell& c, const PairSet& ps, const c128* X, int nx, c
   if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tuning event");
   if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tuning event");
   double best = 1e300;
-  int bmb = 1024;
-  for (int mb : {256, 1024}) {
+  int bmb = 16384;
+  for (int mb : {1024, 4096, 16384}) {
     (void)hipEventRecord(e0, st);
     fock_status s = plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)mb << 20);
     if (s != FOCK_OK) return s;
@@ -120,32 +121,34 @@ static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c1
                                   const c128* M, int ns, c128* out, double scale, bool accumulate, hipStream_t st,
                                   size_t cap) {
   const int nr = c.nr;
+  // a batch holds ntb target k-points x nkb source k-points (the pairs of one
+  // (target, source) k-point pair take per_k bytes): all sources of several targets
+  // when the cap allows, else a block of sources of one target
   const size_t per_k = (size_t)ns * nx * nr * sizeof(c128);
-  int kb = (int)std::max<size_t>(1, cap / std::max<size_t>(per_k, 1));
-  kb = std::min(kb, ps.nsk);
-  kb = std::max(1, std::min(kb, 65535 / std::max(1, ns * nx)));  // grid.y of the batch kernels
-  if ((long)ns * nx > 65535) return fail(FOCK_ERR_SIZE, "too many band pairs per k-point pair (%d x %d)", ns, nx);
-  fock_status s = pl.batch.ensure((size_t)kb * per_k, pl.workspace_cap, "plain-path batch buffer");
+  const long fit = (long)std::max<size_t>(1, cap / std::max<size_t>(per_k, 1));
+  const int nkb_max = (int)std::min<long>(fit, ps.nsk);
+  const int ntb_max = (int)std::max<long>(1, std::min<long>(fit / ps.nsk, ps.ntk));
+  if ((long)ntb_max * nkb_max * ns * nx > (long)INT32_MAX)
+    return fail(FOCK_ERR_SIZE, "pair batch of %d x %d k-points too large", ntb_max, nkb_max);
+  fock_status s = pl.batch.ensure((size_t)ntb_max * nkb_max * per_k, pl.workspace_cap, "plain-path batch buffer");
   if (s != FOCK_OK) return s;
   c128* buf = (c128*)pl.batch.ptr;
   hipError_t e;
   if ((e = pl.prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
-  for (int k = 0; k < ps.ntk; ++k) {
-    const c128* Xk = X + (size_t)k * nx * nr;
-    c128* outk = out + (size_t)k * nx * nr;
-    for (int ks0 = 0; ks0 < ps.nsk; ks0 += kb) {
-      const int nkb = std::min(kb, ps.nsk - ks0);
-      if ((e = launch_pair_product(buf, Xk, P, ks0, nkb, ns, nx, nr, st)) != hipSuccess)
+  for (int kt0 = 0; kt0 < ps.ntk; kt0 += ntb_max) {
+    const int ntb = std::min(ntb_max, ps.ntk - kt0);
+    for (int ks0 = 0; ks0 < ps.nsk; ks0 += nkb_max) {
+      const int nkb = std::min(nkb_max, ps.nsk - ks0);
+      const int nf = ntb * nkb * ns * nx;
+      if ((e = launch_pair_product(buf, X, P, kt0, ntb, ks0, nkb, ns, nx, nr, st)) != hipSuccess)
         return hip_fail(e, "pair product");
-      if ((e = launch_fft3_plain(buf, nkb * ns * nx, c.geom, -1, st)) != hipSuccess)
-        return hip_fail(e, "forward FFT");
-      if ((e = launch_kernel_mul(buf, (const double*)c.K64.ptr, ps.qidx, k, ps.nsk, ks0, nkb, ns * nx, nr, st)) !=
-          hipSuccess)
+      if ((e = launch_fft3_plain(buf, nf, c.geom, -1, st)) != hipSuccess) return hip_fail(e, "forward FFT");
+      if ((e = launch_kernel_mul(buf, (const double*)c.K64.ptr, ps.qidx, kt0, ntb, ps.nsk, ks0, nkb, ns * nx, nr,
+                                 st)) != hipSuccess)
         return hip_fail(e, "kernel multiply");
-      if ((e = launch_fft3_plain(buf, nkb * ns * nx, c.geom, +1, st)) != hipSuccess)
-        return hip_fail(e, "inverse FFT");
-      if ((e = launch_mac(outk, buf, M, ks0, nkb, ns, nx, nr, scale, (accumulate || ks0 > 0) ? 1 : 0, st)) !=
-          hipSuccess)
+      if ((e = launch_fft3_plain(buf, nf, c.geom, +1, st)) != hipSuccess) return hip_fail(e, "inverse FFT");
+      if ((e = launch_mac(out, buf, M, kt0, ntb, ks0, nkb, ns, nx, nr, scale, (accumulate || ks0 > 0) ? 1 : 0,
+                          st)) != hipSuccess)
         return hip_fail(e, "accumulate");
     }
   }

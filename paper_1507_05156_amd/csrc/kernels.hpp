@@ -24,17 +24,19 @@ hipError_t launch_build_table_f64(double* K, const double* qvec, const int* qzer
 hipError_t launch_build_table_fused(float* Kt, const double* K, int nq, int n, hipStream_t st);
 
 // ---- plain FP64 path -----------------------------------------------------
-// batch[((kb*nb + j)*nx + s)][r] = conj(P[ks0+kb][j][r]) * X_k[s][r]
-hipError_t launch_pair_product(c128* batch, const c128* Xk, const c128* P, int ks0, int nkb, int nb, int nx,
-                               int nr, hipStream_t st);
+// A batch holds the pairs of ntb target k-points (kt0 ..) and nkb source k-points (ks0 ..):
+// pair p = ((tb*nkb + kb)*nb + j)*nx + s, each a field of nr values.
+// batch[p][r] = conj(P[ks0+kb][j][r]) * X[kt0+tb][s][r]
+hipError_t launch_pair_product(c128* batch, const c128* X, const c128* P, int kt0, int ntb, int ks0, int nkb, int nb,
+                               int nx, int nr, hipStream_t st);
 // in-place 3D FFT of nfields fields of shape n1 x n2 x n3 (sign -1 forward, +1 inverse, unnormalised)
 hipError_t launch_fft3_plain(c128* data, int nfields, const Geom& g, int sign, hipStream_t st);
-// batch[p][l] *= K[qidx[k*nk + ks0 + kb(p)]][l]
-hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int k, int nk, int ks0, int nkb,
-                             int per_kb, int nr, hipStream_t st);
-// out_k[s][r] = (accumulate ? out_k[s][r] : 0) + scale * sum_{kb,j} M[ks0+kb][j][r] * batch[(kb*nb+j)*nx+s][r]
-hipError_t launch_mac(c128* outk, const c128* batch, const c128* M, int ks0, int nkb, int nb, int nx, int nr,
-                      double scale, int accumulate, hipStream_t st);
+// batch[p][l] *= K[qidx[(kt0+tb)*nk + ks0+kb]][l]
+hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int kt0, int ntb, int nk, int ks0,
+                             int nkb, int per_kb, int nr, hipStream_t st);
+// out[kt0+tb][s][r] = (accumulate ? out : 0) + scale * sum_{kb,j} M[ks0+kb][j][r] * batch[((tb*nkb+kb)*nb+j)*nx+s][r]
+hipError_t launch_mac(c128* out, const c128* batch, const c128* M, int kt0, int ntb, int ks0, int nkb, int nb, int nx,
+                      int nr, double scale, int accumulate, hipStream_t st);
 
 // ---- fused FP32 path -----------------------------------------------------
 struct FusedArgs {

@@ -16,16 +16,22 @@ namespace fockmi {
 
 namespace {
 
-__global__ void pair_product_kernel(c128* __restrict__ batch, const c128* __restrict__ Xk,
-                                    const c128* __restrict__ P, int ks0, int nb, int nx, int nr) {
+// pair p = ((tb * nkb + kb) * nb + j) * nx + s of the batch: target k-point kt0 + tb,
+// source k-point ks0 + kb, band j, target field s
+__global__ void pair_product_kernel(c128* __restrict__ batch, const c128* __restrict__ X, const c128* __restrict__ P,
+                                    int kt0, int ks0, int nkb, int nb, int nx, int nr, long npairs) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;  // (kb*nb + j)*nx + s
   if (r >= nr) return;
-  const int s = p % nx;
-  const int kbj = p / nx;  // kb*nb + j
-  const c128 x = Xk[(long)s * nr + r];
-  const c128 u = P[((long)ks0 * nb + kbj) * nr + r];
-  batch[(long)p * nr + r] = cmulc(u, x);
+  for (long p = blockIdx.y; p < npairs; p += gridDim.y) {
+    const int s = (int)(p % nx);
+    const long q = p / nx;  // (tb * nkb + kb) * nb + j
+    const int j = (int)(q % nb);
+    const long tk = q / nb;  // tb * nkb + kb
+    const int kb = (int)(tk % nkb), tb = (int)(tk / nkb);
+    const c128 x = X[((long)(kt0 + tb) * nx + s) * nr + r];
+    const c128 u = P[((long)(ks0 + kb) * nb + j) * nr + r];
+    batch[p * nr + r] = cmulc(u, x);
+  }
 }
 
 // one thread per line of length N with element stride `inner`; lines are
@@ -116,44 +122,54 @@ hipError_t contig_dispatch(int n, c128* data, long nlines, hipStream_t st) {
 }
 
 __global__ void kernel_mul_kernel(c128* __restrict__ batch, const double* __restrict__ K,
-                                  const int* __restrict__ qidx, int k, int nk, int ks0, int per_kb, int nr) {
+                                  const int* __restrict__ qidx, int kt0, int nk, int ks0, int nkb, int per_kb, int nr,
+                                  long npairs) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
   if (l >= nr) return;
-  const int ks = ks0 + p / per_kb;
-  const double kv = K[(long)qidx[k * nk + ks] * nr + l];
-  c128 v = batch[(long)p * nr + l];
-  v.re *= kv;
-  v.im *= kv;
-  batch[(long)p * nr + l] = v;
+  for (long p = blockIdx.y; p < npairs; p += gridDim.y) {
+    const long tk = p / per_kb;  // tb * nkb + kb
+    const int kb = (int)(tk % nkb), tb = (int)(tk / nkb);
+    const double kv = K[(long)qidx[(long)(kt0 + tb) * nk + ks0 + kb] * nr + l];
+    c128 v = batch[p * nr + l];
+    v.re *= kv;
+    v.im *= kv;
+    batch[p * nr + l] = v;
+  }
 }
 
-__global__ void mac_kernel(c128* __restrict__ outk, const c128* __restrict__ batch, const c128* __restrict__ M,
-                           int ks0, int nkb, int nb, int nx, int nr, double scale, int accumulate) {
+// out[kt0 + tb][s] = (accumulate ? out : 0) + scale * sum_{kb, j} M[ks0 + kb][j] W[tb][kb][j][s]
+__global__ void mac_kernel(c128* __restrict__ out, const c128* __restrict__ batch, const c128* __restrict__ M,
+                           int kt0, int ntb, int ks0, int nkb, int nb, int nx, int nr, double scale, int accumulate) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
   if (r >= nr) return;
-  double are = 0.0, aim = 0.0;
-  for (int kb = 0; kb < nkb; ++kb) {
-    for (int j = 0; j < nb; ++j) {
-      const c128 m = M[((long)(ks0 + kb) * nb + j) * nr + r];
-      const c128 w = batch[((long)(kb * nb + j) * nx + s) * nr + r];
-      are += m.re * w.re - m.im * w.im;
-      aim += m.re * w.im + m.im * w.re;
+  for (int ts = blockIdx.y; ts < ntb * nx; ts += gridDim.y) {
+    const int tb = ts / nx, s = ts % nx;
+    double are = 0.0, aim = 0.0;
+    for (int kb = 0; kb < nkb; ++kb) {
+      for (int j = 0; j < nb; ++j) {
+        const c128 m = M[((long)(ks0 + kb) * nb + j) * nr + r];
+        const c128 w = batch[((((long)tb * nkb + kb) * nb + j) * nx + s) * nr + r];
+        are += m.re * w.re - m.im * w.im;
+        aim += m.re * w.im + m.im * w.re;
+      }
     }
+    c128* o = out + ((long)(kt0 + tb) * nx + s) * nr + r;
+    c128 v = accumulate ? *o : c128{0.0, 0.0};
+    v.re += scale * are;
+    v.im += scale * aim;
+    *o = v;
   }
-  c128 o = accumulate ? outk[(long)s * nr + r] : c128{0.0, 0.0};
-  o.re += scale * are;
-  o.im += scale * aim;
-  outk[(long)s * nr + r] = o;
 }
+
+unsigned grid_y(long n) { return (unsigned)(n < 65535 ? n : 65535); }
 
 }  // namespace
 
-hipError_t launch_pair_product(c128* batch, const c128* Xk, const c128* P, int ks0, int nkb, int nb, int nx,
-                               int nr, hipStream_t st) {
-  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)(nkb * nb * nx));
-  hipLaunchKernelGGL(pair_product_kernel, grid, dim3(256), 0, st, batch, Xk, P, ks0, nb, nx, nr);
+hipError_t launch_pair_product(c128* batch, const c128* X, const c128* P, int kt0, int ntb, int ks0, int nkb, int nb,
+                               int nx, int nr, hipStream_t st) {
+  const long np = (long)ntb * nkb * nb * nx;
+  dim3 grid((unsigned)((nr + 255) / 256), grid_y(np));
+  hipLaunchKernelGGL(pair_product_kernel, grid, dim3(256), 0, st, batch, X, P, kt0, ks0, nkb, nb, nx, nr, np);
   return hipGetLastError();
 }
 
@@ -183,17 +199,19 @@ hipError_t launch_fft3_plain(c128* data, int nfields, const Geom& g, int sign, h
   return ax1(+1);
 }
 
-hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int k, int nk, int ks0, int nkb,
-                             int per_kb, int nr, hipStream_t st) {
-  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)(nkb * per_kb));
-  hipLaunchKernelGGL(kernel_mul_kernel, grid, dim3(256), 0, st, batch, K, qidx, k, nk, ks0, per_kb, nr);
+hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int kt0, int ntb, int nk, int ks0,
+                             int nkb, int per_kb, int nr, hipStream_t st) {
+  const long np = (long)ntb * nkb * per_kb;
+  dim3 grid((unsigned)((nr + 255) / 256), grid_y(np));
+  hipLaunchKernelGGL(kernel_mul_kernel, grid, dim3(256), 0, st, batch, K, qidx, kt0, nk, ks0, nkb, per_kb, nr, np);
   return hipGetLastError();
 }
 
-hipError_t launch_mac(c128* outk, const c128* batch, const c128* M, int ks0, int nkb, int nb, int nx, int nr,
-                      double scale, int accumulate, hipStream_t st) {
-  dim3 grid((unsigned)((nr + 255) / 256), (unsigned)nx);
-  hipLaunchKernelGGL(mac_kernel, grid, dim3(256), 0, st, outk, batch, M, ks0, nkb, nb, nx, nr, scale, accumulate);
+hipError_t launch_mac(c128* out, const c128* batch, const c128* M, int kt0, int ntb, int ks0, int nkb, int nb, int nx,
+                      int nr, double scale, int accumulate, hipStream_t st) {
+  dim3 grid((unsigned)((nr + 255) / 256), grid_y((long)ntb * nx));
+  hipLaunchKernelGGL(mac_kernel, grid, dim3(256), 0, st, out, batch, M, kt0, ntb, ks0, nkb, nb, nx, nr, scale,
+                     accumulate);
   return hipGetLastError();
 }
 

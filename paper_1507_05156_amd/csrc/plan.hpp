@@ -108,7 +108,7 @@ struct Plan {
   std::string tune_path;
   std::vector<Cell> cells;
   size_t workspace_cap = 0;                 // 0 = no cap (FOCKMI_WORKSPACE_CAP overrides)
-  size_t batch_cap = size_t(1) << 30;       // plain path: bytes per pair batch
+  size_t batch_cap = size_t(16) << 30;      // plain path: bytes per pair batch
   int xcd_map = 1;
   DevBuf batch, shadow_x, shadow_p, shadow_m, comp, accs, vu, partial, dotres, srcbuf, srcout;
   DevBuf psi0, phiA, phiB, predb, srcbuf2, kin, vxb, lam, lam2, gtmp, ftmp, phis, norms, red6, vloc_buf;
