@@ -71,23 +71,51 @@ def test_bench_workload_fp32_every_k_vs_fp64(device):
     assert rel.max() < 1e-6
 
 
-def test_batched_workload_sampled_rows(device):
-    """16^3/27 k/8 b, 20^3/64 k/12 b and 24^3/125 k/16 b in one persistent launch."""
-    print("[gpu] full size batched rows", flush=True)
+def _batched_plan(cells, form=None, tmp_path=None):
+    """The three-cell plan; with `form`, that batched form forced through a tuning cache."""
+    import json
+
+    import torch
     from paper_1507_05156_amd.api import Plan
+    if form is None:
+        return Plan(cells, prec="fp32")
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/fp32/batched" + "".join(
+        f"/{arch}/fp32/cell/n{c['n']}x{c['n']}x{c['n']}/nt{len(c['kpts'])}/ns{len(c['kpts'])}/nb{c['nb']}/nx{c['nb']}"
+        for c in cells)
+    path = tmp_path / f"tune_batched_{form}.json"
+    path.write_text(json.dumps({key: {"form": form, "wg_per_cu": 1, "ms": 0}}))
+    return Plan(cells, prec="fp32", tune_cache=str(path))
+
+
+@pytest.mark.parametrize("form", [None, 0])
+def test_batched_workload_sampled_rows(device, tmp_path, form):
+    """16^3/27 k/8 b, 20^3/64 k/12 b and 24^3/125 k/16 b in one captured launch: the
+    default form (each cell's kernel on a forked stream) and the persistent kernel
+    (form 0, forced through the tuning cache), each against the oracle on one row per
+    cell and against each other at every k-point."""
+    print(f"[gpu] full size batched rows, form {form}", flush=True)
+    from tests.oracle_rows import oracle_rows
     cells, us = [], []
     for ci in range(3):
         a, kp, u = synth.workload(4, ci)
         cells.append(dict(n=u.shape[2], a=a, kpts=kp, nb=u.shape[1], omega=OMEGA))
         us.append(u)
-    plan = Plan(cells, prec="fp32")
-    outs = plan.apply_batched([to_dev(u) for u in us])
+    plan = _batched_plan(cells, form, tmp_path)
+    outs = [o.cpu().numpy() for o in plan.apply_batched([to_dev(u) for u in us])]
     for ci, (c, u) in enumerate(zip(cells, us)):
         k, i = c["kpts"].shape[0] - 1, c["nb"] // 2
-        ref = oracle.fock_apply(u, u, c["kpts"], c["a"], OMEGA, rows=[(k, i)])[k, i]
-        e = row_err(outs[ci][k, i].cpu().numpy(), ref)
+        ref = oracle_rows(u, c["kpts"], c["a"], OMEGA, [(k, i)], workers=1)[(k, i)]
+        e = row_err(outs[ci][k, i], ref)
         print(f"  cell {ci} row {(k, i)}: rel err {e:.3e}", flush=True)
         assert e < 1e-6, (ci, e)
+    if form is not None:
+        other = [o.cpu().numpy() for o in _batched_plan(cells).apply_batched([to_dev(u) for u in us])]
+        for ci in range(3):
+            nk = outs[ci].shape[0]
+            d = max(np.linalg.norm(outs[ci][k] - other[ci][k]) / np.linalg.norm(other[ci][k]) for k in range(nk))
+            print(f"  cell {ci}: persistent vs forked, max per-k {d:.3e}", flush=True)
+            assert d < 1e-6
 
 
 def test_differentiation_workload_taylor_step_rows(device):
