@@ -501,11 +501,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "accumulate_dtype": "f64 (Neumaier-compensated k' sums; FP32 band sums)",
+        "accumulate_dtype": "f64 (Neumaier-compensated sums of FP32 partial sums over at most 16 bands)",
         "data": "synthetic seeded orbitals",
         "config": {"workload": f"{n}^3 grid, {round(nk ** (1 / 3))}^3 Gamma-centred k-mesh ({nk} k), {nb} bands, "
                                f"a=10.26 bohr cubic, omega={omega} bohr^-1",
-                   "pairs_per_step": pairs, "ffts_per_step": 2 * pairs, "kernel": "fused FP32 pair kernel"},
+                   "pairs_per_step": pairs, "ffts_per_step": 2 * pairs,
+                   "kernel": "split FP32 pair kernel (each target on two CUs of one XCD)" if n == 32 else "fused FP32 pair kernel"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "split32_kernel" if n == 32 else f"fused_apply_kernel<{n}>", "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,

@@ -52,8 +52,9 @@ typedef enum {
 typedef enum {
   FOCK_FP64 = 0,         /* plain FP64 path: one stage per kernel through HBM */
   FOCK_FP32_COMP = 1,    /* fused pair kernel: complex64 pair FFTs; the sum over the bands j
-                            of one k' in FP32, added into an FP64 running sum over k' with
-                            Neumaier compensation */
+                            of one k' in FP32 over at most 16 bands at a time, each such
+                            partial sum added into an FP64 running sum with Neumaier
+                            compensation, so the FP32 error does not grow with N_b */
   FOCK_FP64_FUSED = 2    /* fused pair kernel in FP64 throughout (complex128 pair FFTs, one FP64
                             sum over all pairs) for cubic grids of length 16, 20 or 24; other
                             cells of such a plan run the plain FP64 stages */

@@ -3,7 +3,8 @@ bench.py times, on outputs the FP64 oracle evaluates one by one.
 
 * 32^3 grid, 6^3 k, 16 bands, FP32 form (the bench workload): sampled output rows,
   each a sum over all 3,456 source orbitals.
-* Three uneven cells in one persistent launch: one sampled row per cell.
+* Three uneven cells in one captured launch, in the default form (each cell's kernel on
+  a forked stream) and in the persistent kernel's form: one sampled row per cell.
 * 24^3 grid, 4^3 k, 16 bands, FP64: one Taylor-4 step, sampled rows.
 * The same cell through 20 checkpointed steps in the fused FP64 form: dE_ex/dA0 by
   the adjoint against central finite differences (about 3 minutes of GPU time).
