@@ -275,7 +275,6 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     sa.xbuf = (c64*)xbuf.ptr;
     sa.flags = (int*)sflags.ptr;
     sa.status = (int*)sstatus.ptr;
-    sa.band_flush = band_flush;
     sa.wait_ticks = split_wait_ticks;
     hipError_t e2 = launch_split32(sa, nwg_split, st);
     if (e2 != hipSuccess) return e2;
@@ -476,7 +475,6 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
     (void)p->tune.load(p->tune_path);
   }
   if (const char* g = std::getenv("FOCKMI_GRAPH")) p->use_graph = std::atoi(g) != 0;
-  if (const char* g = std::getenv("FOCKMI_BAND_FLUSH")) p->band_flush = std::max(1, std::atoi(g));
   if (const char* g = std::getenv("FOCKMI_SPLIT_WAIT_TICKS")) p->split_wait_ticks = std::atol(g);
   {
     hipDeviceProp_t prop;

@@ -90,10 +90,9 @@ size_t fused_acc_scratch_elems(int n, int nslots);  // c64 elements needed in ac
 struct SplitArgs {
   FusedArgs f;          // X, P, M, qidx, out, comp, nk, nx, nb, nitems, scale (accumulate must be 0)
   const float* SD;      // [nq][16384][2]: (S, D) = K(l1') +- K(l1' + 16) at (l2 * 512 + 32 l1' + l3), 1/N_r folded
-  c64* xbuf;            // [nwg/2 pairs][2 halves][2 buffers][16384] exchange buffers
+  c64* xbuf;            // [nwg/2 pairs][2 halves][16384] exchange mailboxes
   int* flags;           // split32_flag_ints(nwg) ints: rendezvous counters, then XCD ids
   int* status;          // [0] abort word, cleared by the launch
-  int band_flush;       // bands per FP32 partial sum (>= 1)
   long wait_ticks;      // bound of one rendezvous wait (100 MHz ticks); < 0 stops the launch at once
 };
 size_t split32_flag_ints(int nwg);

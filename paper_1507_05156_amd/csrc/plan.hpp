@@ -116,7 +116,6 @@ struct Plan {
   DevBuf parts;                             // FP64 part sums of the lockstep form's k' split
   DevBuf xbuf, sflags, sstatus;             // exchange buffers, rendezvous counters, abort word of the split form
   DevBuf fallbacks;                         // split launches that fell back (counted while profiling)
-  int band_flush = 16;                      // bands per FP32 partial sum of the split form (FOCKMI_BAND_FLUSH)
   long split_wait_ticks = 5000000;          // rendezvous bound of the split form, 50 ms (FOCKMI_SPLIT_WAIT_TICKS)
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 4 doubles for reductions

@@ -20,9 +20,11 @@
 //   with S = K(l1') + K(l1' + 16) and D = K(l1') - K(l1' + 16) (table of (S, D)
 //   pairs, 1/N_r folded), after which the inverse DFTs along m2, m3 and the
 //   16-point inverse along m1' give W at the half's points;
-//   acc += M W (the FP32 band sum, in registers), added into the FP64 running
-//   sum with Neumaier compensation every band_flush bands and at the end of
-//   each k'.
+//   acc += M W (the FP32 band sum, in registers). Each element's FP32 partial
+//   sum covers at most 16 consecutive pairs before it is added into the FP64
+//   running sum with Neumaier compensation; the folds are staggered, a few of a
+//   thread's elements every other pair, so that their FP64 loads and stores
+//   are spread over the pairs.
 //
 // Layouts, thread t = 32 hi + lo of 512:
 //   A (loads, MAC): (m2, m3) = (hi + 16 s, lo) for s in {0, 1}, 16 values m1' each;
@@ -55,6 +57,13 @@ constexpr int kHalfElems = kN * kN * kN / 2;  // 16384 points per half
 constexpr int kCtr = 4;                    // ints between rendezvous counters (16 bytes)
 constexpr int kHalfBlock = (1 + 2 * (kT / 64)) * kCtr;  // counters of one half of a pair
 constexpr unsigned kPairBytes = kHalfElems * 8u;
+// staggered FP64 fold: kFoldW of a thread's 32 band-sum elements are folded at
+// every kFoldSp-th pair, so each element is folded once every 16 pairs (4 at
+// every other pair measured 1.5% faster than 2 at every pair on the 32^3 / 216 k
+// / 16-band workload; 8 at every 4th spills)
+constexpr int kFoldW = 4;
+constexpr int kFoldSp = kFoldW / 2;
+static_assert(kFoldW == 2 || kFoldW == 4 || kFoldW == 8, "fold width");
 
 // s + c += x with the rounding error of each addition carried in c (no contraction).
 __device__ __forceinline__ void neumaier2(double& s, double& c, double x) {
@@ -311,17 +320,18 @@ split32_kernel(SplitArgs S) {
       });
       // ---- acc += M W into the FP32 band sums, and, in the same memory phase, the
       // next pair's density conj(P) X into v as each W element is consumed.
-      // Staggered fold into FP64: at pair src (not the last), elements 2f and 2f + 1,
-      // f = src mod 16, add their FP32 partial sums (at most 16 pairs each) to the
-      // FP64 running sum with Neumaier compensation; the last pair's partials go
-      // into the final fold.
-      const int f = src & 15;
-      const bool fold = has_next;
-      const bool fold_prev = src >= 16;  // the two elements were folded before
-      const unsigned fo0 = (unsigned)((((2 * f) % 16) * 2 * NN + ((2 * f) / 16) * NN / 2) * 8);
-      const unsigned fo1 = fo0 + 2 * NN * 8;  // element 2f + 1: m1' one higher
-      c128 fq[2];
-      c64 fc[2];
+      // Staggered fold into FP64: at the last pair of every kFoldSp (not the last
+      // pair of the target), elements kFoldW f .. kFoldW f + kFoldW - 1,
+      // f = (src / kFoldSp) mod (32 / kFoldW), add their FP32 partial sums (at most
+      // 16 pairs each) to the FP64 running sum with Neumaier compensation; the last
+      // pair's partials go into the final fold.
+      const int f = (src / kFoldSp) % (32 / kFoldW);
+      const bool fold = has_next && src % kFoldSp == kFoldSp - 1;
+      const bool fold_prev = src >= 16;  // these elements were folded before
+      // element kFoldW f + k: m1' = (kFoldW f) mod 16 + k, s = (kFoldW f) / 16
+      const unsigned fo0 = (unsigned)((((kFoldW * f) % 16) * 2 * NN + ((kFoldW * f) / 16) * NN / 2) * 8);
+      c128 fq[kFoldW];
+      c64 fc[kFoldW];
       constexpr int GM = 8;
       static_for<32 / GM>([&](auto g) {
         constexpr int G0 = decltype(g)::value * GM;
@@ -340,21 +350,22 @@ split32_kernel(SplitArgs S) {
       });
       if (fold) {
 #pragma clang fp contract(off)
-        if (fold_prev) {
-          fq[0] = ld_c128(rOut, voff16, 2 * fo0);
-          fq[1] = ld_c128(rOut, voff16, 2 * fo1);
-          fc[0] = ld_c64(rComp, voff8, fo0);
-          fc[1] = ld_c64(rComp, voff8, fo1);
-        } else {
-          fq[0] = fq[1] = c128{0.0, 0.0};
-          fc[0] = fc[1] = c64{0.0f, 0.0f};
-        }
-        static_for<16>([&](auto ff) {
+        static_for<kFoldW>([&](auto kk) {
+          constexpr int k = decltype(kk)::value;
+          if (fold_prev) {
+            fq[k] = ld_c128(rOut, voff16, 2 * (fo0 + k * 2 * NN * 8));
+            fc[k] = ld_c64(rComp, voff8, fo0 + k * 2 * NN * 8);
+          } else {
+            fq[k] = c128{0.0, 0.0};
+            fc[k] = c64{0.0f, 0.0f};
+          }
+        });
+        static_for<32 / kFoldW>([&](auto ff) {
           constexpr int F = decltype(ff)::value;
           if (f == F) {
-            static_for<2>([&](auto kk) {
-              constexpr int k = decltype(kk)::value, E = 2 * F + k;
-              const unsigned fo = k ? fo1 : fo0;
+            static_for<kFoldW>([&](auto kk) {
+              constexpr int k = decltype(kk)::value, E = kFoldW * F + k;
+              const unsigned fo = fo0 + k * 2 * NN * 8;
               double sr = fq[k].re, si = fq[k].im, cr = fc[k].re, ci = fc[k].im;
               neumaier2(sr, cr, a.scale * (double)acc[E].re);
               neumaier2(si, ci, a.scale * (double)acc[E].im);
@@ -376,8 +387,8 @@ split32_kernel(SplitArgs S) {
         c64 cq[GF];
         static_for<GF>([&](auto e) {
           constexpr auto E = std::integral_constant<int, G0 + decltype(e)::value>{};
-          // folded before iff its first fold pair (E / 2) came before the last pair
-          if ((E >> 1) < npair_tg - 1) {
+          // folded before iff its first fold pair came before the last pair
+          if ((E / kFoldW) * kFoldSp + kFoldSp - 1 < npair_tg - 1) {
             oq[decltype(e)::value] = ld_c128(rOut, voff16, 2 * offA8(E));
             cq[decltype(e)::value] = ld_c64(rComp, voff8, offA8(E));
           } else {
