@@ -3,7 +3,8 @@
 
 A step is one full application V_x[u] u over every (k, i, k', j) pair of the
 workload (kernel tables resident, orbitals already in HBM), in the fused FP32
-form (complex64 pair FFTs, FP32 band sums, Neumaier-compensated FP64 k' sums).
+form (complex64 pair FFTs; FP32 partial sums over at most 16 bands, added into
+Neumaier-compensated FP64 sums; at 32^3 each target split over two CUs).
 The plain FP64 path runs the same orbitals for the speed-up and the per-k
 error of the FP32 form; the FP64 oracle runs a bounded sample on the host.
 
@@ -32,10 +33,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
 # the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "4a42bd486ba8cb3fa58bf46a90ecc0659d9c6e5e6465df7c0b8641faab06a250",
+    "sources_sha256": "957b0dc369966d2e4f4b99e1ecc5f07a799dfef002564415b49c7c2b1ce89230",
     "workload": 2,
-    "fetch_kib": 1971251750.0625, "write_kib": 3644503671.3125,
-    "fetch_scale": 1.999882466547965, "write_scale": 1.0,
+    "fetch_kib": 1879529590.3125, "write_kib": 3644337373.375,
+    "fetch_scale": 1.99988747276221, "write_scale": 1.0,
 }
 KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/split32.hip",
                   "paper_1507_05156_amd/csrc/fft_reg.hpp",
@@ -170,15 +171,15 @@ def _timed(fn, reps, torch):
 
 def extra_legs(torch, np, synth, Plan, omega, dev, ud_c2, plan32_c2):
     """Timings of the other calls on the path, each on its own workload:
-    the batched persistent launch over three uneven cells (against the same cells
-    launched one by one, and against the plain FP64 path for the error), the FP64
+    the batched launch over three uneven cells in each of its forms (against the
+    same cells launched one by one, and against the plain FP64 path for the error), the FP64
     adjoint and Taylor-4 step at 24^3 / 64 k / 16 bands, and E_x (FP32 form) and
     the FP64 orthonormalisation on the bench workload, the down-sampled sum as
     the paper runs it (12^3 k-points, 4^3 source sub-mesh, 16 bands), the
     work of the field against the energy functional at two time steps, and the
     eigenstates after a pulse with the excited-electron density."""
     out = {}
-    # ------------------------------------------- batched persistent launch (three cells)
+    # ------------------------------------------- batched launch (three cells), every form
     cells, us = [], []
     for ci in range(3):
         a, kp, u = synth.workload(4, ci)
