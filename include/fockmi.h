@@ -54,7 +54,9 @@ typedef enum {
   FOCK_FP32_COMP = 1,    /* fused pair kernel: complex64 pair FFTs; the sum over the bands j
                             of one k' in FP32 over at most 16 bands at a time, each such
                             partial sum added into an FP64 running sum with Neumaier
-                            compensation, so the FP32 error does not grow with N_b */
+                            compensation, so the FP32 error does not grow with N_b.
+                            Cells whose grid is not cubic run the plain stages with
+                            complex64 pair products and FFTs and FP64 sums */
   FOCK_FP64_FUSED = 2    /* fused pair kernel in FP64 throughout (complex128 pair FFTs, one FP64
                             sum over all pairs) for cubic grids of length 16, 20 or 24; other
                             cells of such a plan run the plain FP64 stages */
@@ -283,7 +285,8 @@ fock_status fock_apply_batched(fockmi_plan plan, const void* const* u_occ, const
  * grid form of the fused kernel (one workgroup per target), so for grid
  * lengths up to 24 it gives fock_apply's bits.
  * Errors: FOCK_ERR_SIZE when the cell needs more scratch than the fixed array
- * (about 32 MiB of shadows: e.g. 16^3 with up to ~500 orbitals); FOCK_ERR_ARG as
+ * (about 32 MiB of shadows: e.g. 16^3 with up to ~500 orbitals) or its grid is
+ * not cubic; FOCK_ERR_ARG as
  * fock_apply, and for a plan of another precision. Every call on one GPU uses
  * that GPU's one array: calls that overlap in time on one GPU (other streams,
  * other threads) race and must be serialised by the caller. Stream-ordered. */

@@ -76,18 +76,27 @@ fock_status Plan::check_ready(int cell) const {
 }
 
 // ------------------------------------------------------------------ plumbing
+template <typename T>
 static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P,
                                   const c128* M, int ns, c128* out, double scale, bool accumulate, hipStream_t st,
                                   size_t cap);
+
+// the plain stages in FP64, or in FP32 for an FP32-form cell on a grid that is not cubic
+static fock_status plain_stages(Plan& pl, Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P,
+                                const c128* M, int ns, c128* out, double scale, bool accumulate, hipStream_t st,
+                                size_t cap) {
+  if (c.f32plain) return plain_pipeline<float>(pl, c, ps, X, nx, P, M, ns, out, scale, accumulate, st, cap);
+  return plain_pipeline<double>(pl, c, ps, X, nx, P, M, ns, out, scale, accumulate, st, cap);
+}
 
 fock_status Plan::run_plain(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
                             c128* out, double scale, bool accumulate, hipStream_t st) {
   const std::string key = key_for(c, ps, nx, "plain");
   TuneEntry te;
-  if (tune.get(key, &te)) return plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, accumulate, st,
+  if (tune.get(key, &te)) return plain_stages(*this, c, ps, X, nx, P, M, ns, out, scale, accumulate, st,
                                                 (size_t)te.fields["batch_mb"] << 20);
   if (!tuning || accumulate)
-    return plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, accumulate, st, batch_cap);
+    return plain_stages(*this, c, ps, X, nx, P, M, ns, out, scale, accumulate, st, batch_cap);
   // measure the pair-batch size (each candidate writes the same result)
   hipEvent_t e0, e1;
   hipError_t e;
@@ -97,7 +106,7 @@ fock_status Plan::run_plain(Cell& c, const PairSet& ps, const c128* X, int nx, c
   int bmb = 16384;
   for (int mb : {1024, 4096, 16384}) {
     (void)hipEventRecord(e0, st);
-    fock_status s = plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)mb << 20);
+    fock_status s = plain_stages(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)mb << 20);
     if (s != FOCK_OK) return s;
     (void)hipEventRecord(e1, st);
     if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "tuning sync");
@@ -114,9 +123,10 @@ fock_status Plan::run_plain(Cell& c, const PairSet& ps, const c128* X, int nx, c
   te.fields["ms"] = best;
   tune.put(key, te);
   save_tune();
-  return plain_pipeline(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)bmb << 20);
+  return plain_stages(*this, c, ps, X, nx, P, M, ns, out, scale, false, st, (size_t)bmb << 20);
 }
 
+template <typename T>
 static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P,
                                   const c128* M, int ns, c128* out, double scale, bool accumulate, hipStream_t st,
                                   size_t cap) {
@@ -124,7 +134,7 @@ static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c1
   // a batch holds ntb target k-points x nkb source k-points (the pairs of one
   // (target, source) k-point pair take per_k bytes): all sources of several targets
   // when the cap allows, else a block of sources of one target
-  const size_t per_k = (size_t)ns * nx * nr * sizeof(c128);
+  const size_t per_k = (size_t)ns * nx * nr * sizeof(cx<T>);
   const long fit = (long)std::max<size_t>(1, cap / std::max<size_t>(per_k, 1));
   const int nkb_max = (int)std::min<long>(fit, ps.nsk);
   const int ntb_max = (int)std::max<long>(1, std::min<long>(fit / ps.nsk, ps.ntk));
@@ -132,7 +142,7 @@ static fock_status plain_pipeline(Plan& pl, Cell& c, const PairSet& ps, const c1
     return fail(FOCK_ERR_SIZE, "pair batch of %d x %d k-points too large", ntb_max, nkb_max);
   fock_status s = pl.batch.ensure((size_t)ntb_max * nkb_max * per_k, pl.workspace_cap, "plain-path batch buffer");
   if (s != FOCK_OK) return s;
-  c128* buf = (c128*)pl.batch.ptr;
+  cx<T>* buf = (cx<T>*)pl.batch.ptr;
   hipError_t e;
   if ((e = pl.prof_begin(st)) != hipSuccess) return hip_fail(e, "profile event");
   for (int kt0 = 0; kt0 < ps.ntk; kt0 += ntb_max) {
@@ -349,7 +359,7 @@ void Plan::save_tune() {
 
 fock_status Plan::general(Cell& c, const PairSet& ps, const c128* X, int nx, const c128* P, const c128* M, int ns,
                           c128* out, double scale, bool accumulate, hipStream_t st) {
-  if (prec == FOCK_FP32_COMP) return run_fused(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
+  if (prec == FOCK_FP32_COMP && !c.f32plain) return run_fused(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
   if (c.f64f) return run_fused64(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
   return run_plain(c, ps, X, nx, P, M, ns, out, scale, accumulate, st);
 }
@@ -438,9 +448,6 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
     for (int dd = 0; dd < 3; ++dd)
       if (!valid_len(d.n[dd]))
         return fail(FOCK_ERR_SIZE, "cell %d: grid length %d not in {16, 20, 24, 32}", ci, d.n[dd]);
-    if (prec == FOCK_FP32_COMP && !(d.n[0] == d.n[1] && d.n[1] == d.n[2]))
-      return fail(FOCK_ERR_SIZE, "cell %d: the fused FP32 form needs a cubic grid (got %d x %d x %d)", ci, d.n[0],
-                  d.n[1], d.n[2]);
     if (d.nk < 1 || d.nb < 1) return fail(FOCK_ERR_ARG, "cell %d: nk and nb must be >= 1", ci);
     if (!d.kpts) return fail(FOCK_ERR_ARG, "cell %d: kpts is NULL", ci);
     if (!(d.omega > 0.0) || !std::isfinite(d.omega)) return fail(FOCK_ERR_ARG, "cell %d: omega must be > 0", ci);

@@ -336,10 +336,11 @@ extern "C" fock_status fock_apply_batched(fockmi_plan plan, const void* const* u
   bool any_ds = false;
   for (const Cell& c : p->cells) {
     nmax = std::max(nmax, c.geom.n1);
-    any_ds = any_ds || c.ds;
+    any_ds = any_ds || c.ds || c.f32plain;
   }
   if (p->prec != FOCK_FP32_COMP || nc > kMaxBatchCells || batched_threads(nmax) == 0 || any_ds) {
-    // the plain FP64 path, plans with a 32^3 cell and down-sampled cells run the cells one after another
+    // the plain FP64 path, plans with a 32^3 cell, down-sampled cells and cells that are not
+    // cubic run the cells one after another
     for (int ci = 0; ci < nc; ++ci) {
       if ((s = p->apply_op(p->cells[ci], (const c128*)u_occ[ci], (const c128*)phi[ci], nphi[ci], (c128*)vphi[ci],
                            (hipStream_t)stream)) != FOCK_OK)

@@ -23,19 +23,24 @@ hipError_t launch_build_table_f64(double* K, const double* qvec, const int* qzer
 // Fused-layout FP32 copy for a cubic grid of length n (value index l3, thread t).
 hipError_t launch_build_table_fused(float* Kt, const double* K, int nq, int n, hipStream_t st);
 
-// ---- plain FP64 path -----------------------------------------------------
+// ---- plain path (complex128 batches for FP64, complex64 for the FP32 form on non-cubic grids)
 // A batch holds the pairs of ntb target k-points (kt0 ..) and nkb source k-points (ks0 ..):
-// pair p = ((tb*nkb + kb)*nb + j)*nx + s, each a field of nr values.
-// batch[p][r] = conj(P[ks0+kb][j][r]) * X[kt0+tb][s][r]
-hipError_t launch_pair_product(c128* batch, const c128* X, const c128* P, int kt0, int ntb, int ks0, int nkb, int nb,
+// pair p = ((tb*nkb + kb)*nb + j)*nx + s, each a field of nr values. T is double or float.
+// batch[p][r] = conj(P[ks0+kb][j][r]) * X[kt0+tb][s][r] (inputs rounded to T)
+template <typename T>
+hipError_t launch_pair_product(cx<T>* batch, const c128* X, const c128* P, int kt0, int ntb, int ks0, int nkb, int nb,
                                int nx, int nr, hipStream_t st);
 // in-place 3D FFT of nfields fields of shape n1 x n2 x n3 (sign -1 forward, +1 inverse, unnormalised)
-hipError_t launch_fft3_plain(c128* data, int nfields, const Geom& g, int sign, hipStream_t st);
+template <typename T>
+hipError_t launch_fft3_plain(cx<T>* data, int nfields, const Geom& g, int sign, hipStream_t st);
 // batch[p][l] *= K[qidx[(kt0+tb)*nk + ks0+kb]][l]
-hipError_t launch_kernel_mul(c128* batch, const double* K, const int* qidx, int kt0, int ntb, int nk, int ks0,
+template <typename T>
+hipError_t launch_kernel_mul(cx<T>* batch, const double* K, const int* qidx, int kt0, int ntb, int nk, int ks0,
                              int nkb, int per_kb, int nr, hipStream_t st);
 // out[kt0+tb][s][r] = (accumulate ? out : 0) + scale * sum_{kb,j} M[ks0+kb][j][r] * batch[((tb*nkb+kb)*nb+j)*nx+s][r]
-hipError_t launch_mac(c128* out, const c128* batch, const c128* M, int kt0, int ntb, int ks0, int nkb, int nb, int nx,
+// (FP64 products and sums)
+template <typename T>
+hipError_t launch_mac(c128* out, const cx<T>* batch, const c128* M, int kt0, int ntb, int ks0, int nkb, int nb, int nx,
                       int nr, double scale, int accumulate, hipStream_t st);
 
 // ---- fused FP32 path -----------------------------------------------------

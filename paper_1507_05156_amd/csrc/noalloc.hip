@@ -66,6 +66,7 @@ extern "C" fock_status fock_apply_noalloc(fockmi_plan plan, int cell, const void
   if (s != FOCK_OK) return s;
   if (p->prec != FOCK_FP32_COMP) return fail(FOCK_ERR_ARG, "fock_apply_noalloc needs a FOCK_FP32_COMP plan");
   Cell& c = p->cells[cell];
+  if (c.f32plain) return fail(FOCK_ERR_SIZE, "fock_apply_noalloc needs a cubic grid");
   if (!u_occ || !phi || !vphi) return fail(FOCK_ERR_ARG, "NULL device pointer");
   if (!aligned16(u_occ) || !aligned16(phi) || !aligned16(vphi))
     return fail(FOCK_ERR_ARG, "device pointers must be 16-byte aligned");

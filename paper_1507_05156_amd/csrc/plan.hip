@@ -135,7 +135,10 @@ fock_status Plan::init_cell(Cell& c, const fock_cell_desc& d, int index) {
   if ((e = launch_build_table_f64((double*)c.K64.ptr, (const double*)c.qvec.ptr, (const int*)c.qzero.ptr, c.nq,
                                   c.geom, c.omega, 1.0 / c.nr, 0)) != hipSuccess)
     return hip_fail(e, "kernel table");
-  if (prec == FOCK_FP32_COMP) {
+  if (prec == FOCK_FP32_COMP && !(c.geom.n1 == c.geom.n2 && c.geom.n2 == c.geom.n3)) {
+    // the fused kernels take cubic grids; this cell runs the plain stages in FP32
+    c.f32plain = true;
+  } else if (prec == FOCK_FP32_COMP) {
     if ((s = c.Kt.ensure((size_t)c.nq * c.nr * sizeof(float), 0, "FP32 kernel tables")) != FOCK_OK) return s;
     if ((e = launch_build_table_fused((float*)c.Kt.ptr, (const double*)c.K64.ptr, c.nq, c.geom.n1, 0)) !=
         hipSuccess)

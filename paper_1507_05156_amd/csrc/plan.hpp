@@ -54,6 +54,7 @@ struct Cell {
   DevBuf SD;                  // float[nq][nr/2][2], (S, D) pairs of the split 32^3 form (FP32 plans, n = 32)
   DevBuf Kt64;                // double[nq][nr], fused FP64 kernel layout (FP64-fused plans)
   bool f64f = false;          // this cell runs the fused FP64 kernel
+  bool f32plain = false;      // an FP32-form cell on a grid that is not cubic: the plain stages in FP32
   DevBuf kvec;                // double[nk][3] k-points on the device
   // down-sampling: the source sub-mesh S (all k-points when ds is false)
   bool ds = false;

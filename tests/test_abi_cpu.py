@@ -68,12 +68,16 @@ def test_plan_create_rejects_bad_cells(kw, status):
     assert lib.fock_last_error()
 
 
-def test_fp32_form_needs_cubic_grid():
+@pytest.mark.parametrize("prec", ["FOCK_FP32_COMP", "FOCK_FP64_FUSED"])
+def test_other_forms_check_grid_lengths(prec):
+    """Every precision form takes the same grid lengths (a grid that is not cubic is
+    accepted; it runs the plain stages), and rejects the others before any device call."""
     lib = N.lib()
-    d, keep = _desc(n=(16, 20, 16))
+    d, keep = _desc(n=(16, 20, 18))
     h = C.c_void_p()
-    assert lib.fock_plan_create(C.byref(d), 1, N.FOCK_FP32_COMP, None, C.byref(h)) == N.FOCK_ERR_SIZE
-    assert b"cubic" in lib.fock_last_error()
+    assert lib.fock_plan_create(C.byref(d), 1, getattr(N, prec), None, C.byref(h)) == N.FOCK_ERR_SIZE
+    assert h.value is None
+    assert b"grid length 18" in lib.fock_last_error()
 
 
 def test_null_arguments():

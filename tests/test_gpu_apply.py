@@ -70,15 +70,29 @@ def test_each_grid_ragged_counts(device, n, prec):
     assert rel_per_k(got, ref) < TOL[prec]
 
 
-def test_noncubic_grid_fp64(device):
-    print("[gpu] noncubic fp64", flush=True)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64f"])
+def test_noncubic_grid(device, prec):
+    """A 16 x 20 x 24 grid in an orthorhombic cell: every form runs the plain stages
+    (the FP32 form with complex64 pair products and FFTs), for the application, E_x and
+    the adjoint."""
+    print(f"[gpu] noncubic {prec}", flush=True)
     cell = np.diag([10.26, 11.0, 12.5])
     kp = synth.gamma_mesh(2, cell, 1, 1)
     u = synth.orbitals((16, 20, 24), cell, kp, 2, seed=301)
     ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
-    plan = make_plan(cell, kp, 2, (16, 20, 24), "fp64")
-    got = plan.apply(to_dev(u)).cpu().numpy()
-    assert rel_per_k(got, ref) < 1e-10
+    plan = make_plan(cell, kp, 2, (16, 20, 24), prec)
+    d = to_dev(u)
+    got = plan.apply(d).cpu().numpy()
+    assert rel_per_k(got, ref) < TOL[prec]
+    ex = plan.energy(d)
+    ex_ref = oracle.exchange_energy(u, kp, cell, OMEGA, V=ref)
+    assert abs(ex.real - ex_ref.real) < TOL[prec] * abs(ex_ref.real)
+    phi = synth.random_fields((2, 3, 16, 20, 24), seed=302)
+    g = synth.random_fields((2, 3, 16, 20, 24), seed=303)
+    gu_ref, gp_ref = oracle.fock_vjp(u, phi, g, kp, cell, OMEGA)
+    gu, gp = plan.vjp(d, to_dev(phi), to_dev(g))
+    assert rel_per_k(gu.cpu().numpy(), gu_ref) < TOL[prec]
+    assert rel_per_k(gp.cpu().numpy(), gp_ref) < TOL[prec]
 
 
 def test_single_kpoint_single_band(device):
