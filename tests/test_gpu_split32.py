@@ -124,3 +124,36 @@ def test_split_vjp_and_energy_gradient(device):
     assert rel_per_k(ge, oracle.energy_grad(u, kp, cell, OMEGA)) < 1e-6
     assert plan.profile_fallbacks() == 0
     plan.profile(False)
+
+
+def test_split_in_kernel_timeout_falls_back(device):
+    """A real-time limit of one tick (10 ns) on each rendezvous: the waits time out inside
+    the kernel (not the host-forced stop), the launch sets its abort word, every
+    workgroup leaves at its next wait, and the lockstep form behind it gives the result."""
+    print("[gpu] split 32^3 in-kernel timeout", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell, 1, 1)
+    u = synth.orbitals(32, cell, kp, 3, seed=840)
+    plan = plan32(kp, 3, cell, FOCKMI_SPLIT_WAIT_TICKS=1)
+    plan.profile(True)
+    got = plan.apply(to_dev(u)).cpu().numpy()
+    assert plan.profile_fallbacks() == 1
+    plan.profile(False)
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    assert rel_per_k(got, ref) < 1e-6
+
+
+def test_split_single_target_single_pair(device):
+    """Gamma only and one band: one target, one pair (no staggered fold at all, the final
+    fold takes every element), 127 of the 128 CU pairs without work."""
+    print("[gpu] split 32^3 one pair", flush=True)
+    cell = synth.cubic_cell()
+    kp = np.zeros((1, 3))
+    u = synth.orbitals(32, cell, kp, 1, seed=850)
+    plan = plan32(kp, 1, cell)
+    plan.profile(True)
+    got = plan.apply(to_dev(u)).cpu().numpy()
+    assert plan.profile_fallbacks() == 0
+    plan.profile(False)
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    assert rel_per_k(got, ref) < 1e-6
