@@ -30,7 +30,11 @@
 //   A (loads, MAC): (m2, m3) = (hi + 16 s, lo) for s in {0, 1}, 16 values m1' each;
 //   B: (l1', m2) = (hi, lo), the line along m3;
 //   C: (l1', l3) = (hi, lo), the line along m2 (exchange and kernel layout).
-// LDS carries the A <-> B and B <-> C transposes of the half field (132 KiB).
+// LDS carries the A <-> B and B <-> C transposes of the half field (132 KiB) in
+// one array [l1'][m2][m3 or l3] (rows padded to 33). Every phase writes its
+// values back to the very slots it read, so a slot is only ever rewritten by the
+// thread that last read it, and each transpose needs one barrier (between its
+// writes and the next layout's reads), four per pair.
 //
 // The two workgroups of a pair are blocks b and b + 8 of the launch (blocks are
 // dispatched round-robin over the 8 XCDs, so both run on XCD b mod 8); each
@@ -168,11 +172,11 @@ split32_kernel(SplitArgs S) {
   if (!sh_go) return;
   int npub = 0;  // pairs exchanged so far
 
-  // per-thread LDS bases (bytes); layouts as in the header
-  //   A side of A<->B: element (s, m1') at ((m1' 32 + hi + 16 s) 33 + lo) 8
-  //   B side of A<->B: element m3 at (t 33 + m3) 8
-  //   B side of B<->C: element l3 at ((hi 32 + l3) 33 + lo) 8
-  //   C side of B<->C: element m2 at (t 33 + m2) 8
+  // per-thread LDS bases (bytes) into the array [l1'][m2][m3 or l3] (33 per row);
+  // layouts as in the header
+  //   A: element (s, m1') at ((m1' 32 + hi + 16 s) 33 + lo) 8
+  //   B: element m3 or l3 at (t 33 + m3) 8
+  //   C: element m2 at ((hi 32 + m2) 33 + lo) 8
   const unsigned la = (unsigned)((hi * 33 + lo) * 8);
   const unsigned lb = (unsigned)(t * 33 * 8);
   const unsigned lbc = (unsigned)((hi * 32 * 33 + lo) * 8);
@@ -230,22 +234,21 @@ split32_kernel(SplitArgs S) {
         const unsigned bb = opaque(lb);
         static_for<32>([&](auto e) { v[decltype(e)::value] = lds_at<decltype(e)::value * 8>(lds, bb); });
       }
-      __syncthreads();
       fft<32, -1, true>(v);
-      // ---- B -> C; meanwhile thread 0 checks that the other half has read this
-      // half's previous mailbox contents (usually long done), before anyone rewrites it
+      // ---- B -> C: B writes back to the slots it read; meanwhile each wave checks
+      // that the other half's wave has read this wave's previous mailbox contents
+      // (usually long done), before it rewrites them
       {
-        const unsigned bb = opaque(lbc);
-        static_for<32>([&](auto e) { lds_at<decltype(e)::value * 33 * 8>(lds, bb) = v[decltype(e)::value]; });
+        const unsigned bb = opaque(lb);
+        static_for<32>([&](auto e) { lds_at<decltype(e)::value * 8>(lds, bb) = v[decltype(e)::value]; });
       }
       ++npub;
       if (!wait_for(2 + 2 * w, npub - 1)) sh_stop = 1;
       __syncthreads();
       {
-        const unsigned bb = opaque(lb);
-        static_for<32>([&](auto e) { v[decltype(e)::value] = lds_at<decltype(e)::value * 8>(lds, bb); });
+        const unsigned bb = opaque(lbc);
+        static_for<32>([&](auto e) { v[decltype(e)::value] = lds_at<decltype(e)::value * 33 * 8>(lds, bb); });
       }
-      __syncthreads();
       fft<32, -1, true>(v);
       // ---- exchange: this half's E_c out, the other half's in. The first group
       // of (S, D) values is loaded ahead: it does not depend on the other half.
@@ -287,18 +290,17 @@ split32_kernel(SplitArgs S) {
       __hip_atomic_store(mine + (2 + 2 * w) * kCtr, npub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_sched_barrier(0);
       fft<32, +1, true>(v);
-      // ---- C -> B (after its first barrier, a stop requested by any wave is seen by all)
+      // ---- C -> B (after its barrier, a stop requested by any wave is seen by all)
       {
-        const unsigned bb = opaque(lb);
-        static_for<32>([&](auto e) { lds_at<decltype(e)::value * 8>(lds, bb) = v[decltype(e)::value]; });
+        const unsigned bb = opaque(lbc);
+        static_for<32>([&](auto e) { lds_at<decltype(e)::value * 33 * 8>(lds, bb) = v[decltype(e)::value]; });
       }
       __syncthreads();
       if (sh_stop) return;
       {
-        const unsigned bb = opaque(lbc);
-        static_for<32>([&](auto e) { v[decltype(e)::value] = lds_at<decltype(e)::value * 33 * 8>(lds, bb); });
+        const unsigned bb = opaque(lb);
+        static_for<32>([&](auto e) { v[decltype(e)::value] = lds_at<decltype(e)::value * 8>(lds, bb); });
       }
-      __syncthreads();
       fft<32, +1, true>(v);
       // ---- B -> A
       {
@@ -310,7 +312,6 @@ split32_kernel(SplitArgs S) {
         constexpr int E = decltype(e)::value, s = E / 16, m = E % 16;
         v[E] = lds_far<(unsigned)((m * 32 * 33 + s * 16 * 33) * 8)>(lds, la);
       });
-      __syncthreads();
       static_for<2>([&](auto g) {
         constexpr int G0 = decltype(g)::value * 16;
         c64 w[16];
