@@ -143,11 +143,11 @@ struct XcdLockstep {
 
 // One work item (target field X[kt][s]) of the fused pair computation, run by
 // the N*N threads t = 0 .. N*N-1 of one thread group, with `lds` its own LDS
-// region. Twin threads (twin = true) repeat the work of thread t of a real
-// group (same loads, same LDS values to the same addresses, which keeps every
-// wave on the same straight-line code); their FP64 stores are steered past the
-// end of the buffer, where raw buffer stores are dropped. `item` must be
-// uniform over each wave.
+// region. Twin threads (twin = true) run the code of thread t of a real group
+// (the same global loads, which keeps every wave on the same straight-line
+// code) in an LDS region of their own, so their values are meaningless; their
+// FP64 stores are steered past the end of the buffer, where raw buffer stores
+// are dropped. `item` must be uniform over each wave.
 template <int N, class Hook>
 __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc_slot, c64* __restrict__ lds,
                                            int t, bool twin, Hook& hook, int part = 0) {
@@ -172,16 +172,25 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   const int lrow = chi % NBK;
 
   // LDS byte offsets of this thread's elements in the four transposes:
-  //   x side of x<->y : element l1 at lx + l1 * SX        (SX = N*H*8)
-  //   y side of x<->y : element m2 at ly + m2 * H*8
+  //   x side of x<->y : element l1 at lx + l1 * SX
+  //   y side of x<->y : element m2 at ly + m2 * SY
   //   y side of y<->z : element l2 at lyz + l2 * (N+1)*8
   //   z side of y<->z : element m3 at lz + m3 * 8
-  // Only the x side spans more than 64 KiB; its elements from L1S on are
-  // addressed from a second base.
-  constexpr unsigned SX = (unsigned)(N * H * 8);
+  // With one round (N <= 24) both transposes use one array [l1][m2 or l2][m3]
+  // with rows padded to N+1 (SX = N*(N+1)*8, SY = (N+1)*8, and ly = lyz): every
+  // phase then writes its values back to the slots it read, a slot is rewritten
+  // only by the thread that last read it, and each transpose needs one barrier
+  // (twins must therefore work in an LDS region of their own). With two rounds
+  // (N = 32) the x<->y array is [l1][m2][m3 of the round]
+  // (SX = N*H*8, SY = H*8) and the rounds share it, so each transpose keeps a
+  // second barrier before the next round overwrites it. Only the x side spans
+  // more than 64 KiB; its elements from L1S on are addressed from a second base.
+  constexpr bool INPLACE = NPH == 1;
+  constexpr unsigned SX = INPLACE ? (unsigned)(N * (N + 1) * 8) : (unsigned)(N * H * 8);
+  constexpr unsigned SY = INPLACE ? (unsigned)((N + 1) * 8) : (unsigned)(H * 8);
   constexpr int L1S = (int)((65535u / SX) + 1) < N ? (int)((65535u / SX) + 1) : N;
-  const unsigned lx0 = (unsigned)((chi * H + hl) * 8);
-  const unsigned ly0 = (unsigned)((chi * N * H + hl) * 8);
+  const unsigned lx0 = INPLACE ? (unsigned)((chi * (N + 1) + hl) * 8) : (unsigned)((chi * H + hl) * 8);
+  const unsigned ly0 = INPLACE ? (unsigned)((chi * N * (N + 1) + hl) * 8) : (unsigned)((chi * N * H + hl) * 8);
   const unsigned lyz0 = (unsigned)((lrow * N * (N + 1) + clo) * 8);
   const unsigned lz0 = (unsigned)((lrow * N + clo) * (N + 1) * 8);
 
@@ -254,9 +263,9 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
         __syncthreads();
         if (grp == g) {
           const unsigned b = opaque(ly0);
-          static_for<N>([&](auto m2) { v[m2] = lds_at<decltype(m2)::value * H * 8>(lds, b); });
+          static_for<N>([&](auto m2) { v[m2] = lds_at<decltype(m2)::value * SY>(lds, b); });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, -1>(v);
       // y -> z
@@ -271,7 +280,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
           const unsigned b = opaque(lz0);
           static_for<N>([&](auto m3) { v[m3] = lds_at<decltype(m3)::value * 8>(lds, b); });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, -1>(v);
       static_for<(N + grp_k<N>() - 1) / grp_k<N>()>([&](auto cc) {
@@ -294,7 +303,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
           const unsigned b = opaque(lyz0);
           static_for<N>([&](auto l2) { v[l2] = lds_at<decltype(l2)::value * (N + 1) * 8>(lds, b); });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, +1>(v);
       // y -> x
@@ -302,7 +311,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
       for (int g = 0; g < NPH; ++g) {
         if (grp == g) {
           const unsigned b = opaque(ly0);
-          static_for<N>([&](auto m2) { lds_at<decltype(m2)::value * H * 8>(lds, b) = v[m2]; });
+          static_for<N>([&](auto m2) { lds_at<decltype(m2)::value * SY>(lds, b) = v[m2]; });
         }
         __syncthreads();
         if (grp == g) {
@@ -313,7 +322,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
             else v[L] = lds_at<(L - L1S) * SX>(lds, b1);
           });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, +1>(v);
 
@@ -502,13 +511,17 @@ __global__ void add_parts_kernel(c128* __restrict__ out, const c128* __restrict_
 // An entry runs the code of its cell's grid length: 24^3 on all 576 threads,
 // 20^3 on 400 (the rest are twins), and 16^3 on two groups of 256 threads, one
 // target each with its own LDS region (a single target leaves the second group
-// to twins).
+// to twins). Twins work in LDS regions of their own (their values are never
+// used), so that the one-barrier transposes of the real groups stay race-free.
 template <int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 fused_batched_kernel(BatchArgs B) {
   static_assert(NT == 576, "the persistent kernel serves grid lengths up to 24");
-  static_assert(2 * fused_lds_elems<16>() <= fused_lds_elems<24>(), "two 16^3 regions must fit");
-  __shared__ c64 lds[fused_lds_elems<24>()];
+  // regions: 24^3 one; 20^3 real threads and twins; 16^3 two targets and twins
+  constexpr int kE24 = fused_lds_elems<24>(), kE20 = 2 * fused_lds_elems<20>(), kE16 = 3 * fused_lds_elems<16>();
+  constexpr int kLdsElems = kE24 > kE20 ? (kE24 > kE16 ? kE24 : kE16) : (kE20 > kE16 ? kE20 : kE16);
+  static_assert(kLdsElems * 8 <= 160 * 1024, "LDS of the persistent kernel");
+  __shared__ c64 lds[kLdsElems];
   __shared__ int it_sh;
   NoPairHook nh;
   int sq = blockIdx.x % kBatchQueues;  // only thread 0 uses these two
@@ -538,13 +551,17 @@ fused_batched_kernel(BatchArgs B) {
     const int tr = threadIdx.x;
     switch (a.n) {
       case 16: {
-        const int g = tr / 256;  // groups are whole waves
+        const int g = tr / 256;  // groups are whole waves; group g works in LDS region g
         const bool second = item2 >= 0 && g == 1;
-        fused_item<16>(a, second ? item2 : item, blockIdx.x, second ? lds + fused_lds_elems<16>() : lds, tr % 256,
+        fused_item<16>(a, second ? item2 : item, blockIdx.x, lds + g * fused_lds_elems<16>(), tr % 256,
                        !(g == 0 || second), nh);
         break;
       }
-      case 20: fused_item<20>(a, item, blockIdx.x, lds, tr % 400, tr >= 400, nh); break;
+      case 20: {
+        const bool twin = tr >= 400;
+        fused_item<20>(a, item, blockIdx.x, twin ? lds + fused_lds_elems<20>() : lds, tr % 400, twin, nh);
+        break;
+      }
       default: fused_item<24>(a, item, blockIdx.x, lds, tr, false, nh); break;
     }
   }
