@@ -87,11 +87,17 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
   const int lrow = chi % NBK;
 
   // LDS byte offsets of this thread's elements in the four transposes (16-byte elements);
-  // the x side of x<->y spans more than 64 KiB and uses a second base from L1S on
-  constexpr unsigned SX = (unsigned)(N * H * 16);
+  // the x side of x<->y spans more than 64 KiB and uses a second base from L1S on.
+  // With one round (N <= 20) both transposes use one array [l1][m2 or l2][m3] with
+  // rows padded to N+1, every phase writes its values back to the slots it read,
+  // and each transpose needs one barrier; with two rounds (N = 24) the rounds share
+  // the x<->y array and each transpose keeps a second barrier.
+  constexpr bool INPLACE = NPH == 1;
+  constexpr unsigned SX = INPLACE ? (unsigned)(N * (N + 1) * 16) : (unsigned)(N * H * 16);
+  constexpr unsigned SY = INPLACE ? (unsigned)((N + 1) * 16) : (unsigned)(H * 16);
   constexpr int L1S = (int)((65535u / SX) + 1) < N ? (int)((65535u / SX) + 1) : N;
-  const unsigned lx0 = (unsigned)((chi * H + hl) * 16);
-  const unsigned ly0 = (unsigned)((chi * N * H + hl) * 16);
+  const unsigned lx0 = INPLACE ? (unsigned)((chi * (N + 1) + hl) * 16) : (unsigned)((chi * H + hl) * 16);
+  const unsigned ly0 = INPLACE ? (unsigned)((chi * N * (N + 1) + hl) * 16) : (unsigned)((chi * N * H + hl) * 16);
   const unsigned lyz0 = (unsigned)((lrow * N * (N + 1) + clo) * 16);
   const unsigned lz0 = (unsigned)((lrow * N + clo) * (N + 1) * 16);
 
@@ -147,9 +153,9 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
         __syncthreads();
         if (grp == g) {
           const unsigned b = opaque(ly0);
-          static_for<N>([&](auto m2) { v[m2] = lds_at<decltype(m2)::value * H * 16>(lds, b); });
+          static_for<N>([&](auto m2) { v[m2] = lds_at<decltype(m2)::value * SY>(lds, b); });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, -1>(v);
       // y -> z
@@ -164,7 +170,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
           const unsigned b = opaque(lz0);
           static_for<N>([&](auto m3) { v[m3] = lds_at<decltype(m3)::value * 16>(lds, b); });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, -1>(v);
       static_for<N / G>([&](auto cc) {
@@ -187,7 +193,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
           const unsigned b = opaque(lyz0);
           static_for<N>([&](auto l2) { v[l2] = lds_at<decltype(l2)::value * (N + 1) * 16>(lds, b); });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, +1>(v);
       // y -> x
@@ -195,7 +201,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
       for (int g = 0; g < NPH; ++g) {
         if (grp == g) {
           const unsigned b = opaque(ly0);
-          static_for<N>([&](auto m2) { lds_at<decltype(m2)::value * H * 16>(lds, b) = v[m2]; });
+          static_for<N>([&](auto m2) { lds_at<decltype(m2)::value * SY>(lds, b) = v[m2]; });
         }
         __syncthreads();
         if (grp == g) {
@@ -206,7 +212,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
             else v[L] = lds_at<(L - L1S) * SX>(lds, b1);
           });
         }
-        __syncthreads();
+        if constexpr (!INPLACE) __syncthreads();
       }
       fft<N, +1>(v);
 
