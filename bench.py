@@ -31,14 +31,12 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # Device-memory traffic of one fused 32^3 launch, from two rocprofv3 --pmc runs of
 # this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
-# the kernel sources whose digest is recorded; a changed kernel reports null. (The
-# digest was renewed once after a change to kernels.hpp that left the kernel's
-# gfx950 assembly identical.)
+# the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "83aa130992737dd4ab8680d1be193f46e5b93290d65f579e2d3937cd6ec09a37",
+    "sources_sha256": "c97c2aed55ea4e0eb478611530fb4b319c7cdd8155c24819411363784f899456",
     "workload": 2,
-    "fetch_kib": 1879529590.3125, "write_kib": 3644337373.375,
-    "fetch_scale": 1.99988747276221, "write_scale": 1.0,
+    "fetch_kib": 1873621141.4375, "write_kib": 3644336685.75,
+    "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
 }
 KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/fused.hip", "paper_1507_05156_amd/csrc/split32.hip",
                   "paper_1507_05156_amd/csrc/fft_reg.hpp",
