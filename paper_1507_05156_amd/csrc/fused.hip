@@ -48,6 +48,18 @@ constexpr bool fused_acc_in_regs() {
   return N <= 24;
 }
 
+// The target X is loaded once per work item and held in registers (N values per
+// thread) where they fit; otherwise it is re-read with every pair's density. At
+// 16^3 the kernel keeps four waves per SIMD with X in registers (127 VGPRs), and
+// the X re-reads, one private field per workgroup and pair, had filled the L2
+// (the paper's down-sampled 16^3 setting: 386.5 -> 242.6 ms). At 20^3 the four-wave
+// variant spills and the two-wave one loses a workgroup per CU; at 24^3 the line
+// leaves no room.
+template <int N>
+constexpr bool fused_x_in_regs() {
+  return N == 16;
+}
+
 // Global loads are issued in groups whose results are consumed only after the
 // whole group is in flight, so a pair costs a few memory round trips instead
 // of one per line element. Group sizes per grid length: pair-product operands,
@@ -158,6 +170,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   constexpr int TPG = NTI / NPH;   // threads per round
   constexpr int NBK = N / NPH;     // l1 values per round of the y<->z transpose
   constexpr bool ACCREG = fused_acc_in_regs<N>();
+  constexpr bool XREG = fused_x_in_regs<N>();
   item = __builtin_amdgcn_readfirstlane(item);
   // round indices are wave-uniform (rounds are whole waves: 512 and 256 threads
   // at N = 32, a single round below); readfirstlane lets the compiler branch on
@@ -220,6 +233,8 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
   const rsrc_t rAcc = make_rsrc(ACCREG ? a.X : a.accs + (long)acc_slot * NR, ACCREG ? 0u : FB64);
 
   c64 acc[ACCREG ? N : 1];
+  c64 xr[XREG ? N : 1];
+  if constexpr (XREG) static_for<N>([&](auto m1) { xr[m1] = ld_c64(rX, voff_x, (unsigned)(decltype(m1)::value * NTI * 8)); });
 
   for (int ks = ks0; ks < ks1; ++ks) {
     const int qi = __builtin_amdgcn_readfirstlane(a.qidx[kt * a.nk + ks]);
@@ -243,7 +258,8 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int item, int acc
         static_for<CN>([&](auto q) {
           const unsigned so = (unsigned)((C0 + decltype(q)::value) * NTI * 8);
           p[q] = ld_c64(rP, voff_x, so);
-          x[q] = ld_c64(rX, voff_x, so);
+          if constexpr (XREG) x[q] = xr[C0 + decltype(q)::value];
+          else x[q] = ld_c64(rX, voff_x, so);
         });
         __builtin_amdgcn_sched_barrier(0);
         static_for<CN>([&](auto q) { v[C0 + decltype(q)::value] = cmulc(p[q], x[q]); });
