@@ -29,6 +29,13 @@ constexpr bool f64_acc_in_regs() {
   return N <= 20;
 }
 
+// the target held in registers for the whole work item (see the FP32 kernel):
+// at 16^3 two 256-thread workgroups per CU leave room for it
+template <int N>
+constexpr bool f64_x_in_regs() {
+  return N == 16;
+}
+
 template <int N>
 constexpr int f64_lds_elems() {
   constexpr int NPH = f64_nph<N>();
@@ -69,6 +76,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
   constexpr int TPG = NTI / NPH;  // threads per round
   constexpr int NBK = N / NPH;    // l1 values per round of the y<->z transpose
   constexpr bool ACCREG = f64_acc_in_regs<N>();
+  constexpr bool XREG = f64_x_in_regs<N>();
   constexpr int G = f64_grp<N>();
   static_assert(N % G == 0, "load groups must tile the line");
 
@@ -115,6 +123,8 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
   const rsrc_t rAcc = make_rsrc(ACCREG ? a.out : a.accs + (long)acc_slot * NR, ACCREG ? 0u : FB);
 
   c128 acc[ACCREG ? N : 1];
+  c128 xr[XREG ? N : 1];
+  if constexpr (XREG) static_for<N>([&](auto m1) { xr[m1] = ld_c128(rX, voff, (unsigned)(decltype(m1)::value * NTI * 16)); });
   if constexpr (ACCREG) {
 #pragma unroll
     for (int m1 = 0; m1 < N; ++m1) acc[m1] = c128{0.0, 0.0};
@@ -133,7 +143,8 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
         static_for<G>([&](auto q) {
           const unsigned so = (unsigned)((C0 + decltype(q)::value) * NTI * 16);
           p[q] = ld_c128(rP, voff, so);
-          x[q] = ld_c128(rX, voff, so);
+          if constexpr (XREG) x[q] = xr[C0 + decltype(q)::value];
+          else x[q] = ld_c128(rX, voff, so);
         });
         __builtin_amdgcn_sched_barrier(0);
         static_for<G>([&](auto q) { v[C0 + decltype(q)::value] = cmulc(p[q], x[q]); });
