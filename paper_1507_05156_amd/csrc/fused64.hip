@@ -29,6 +29,19 @@ constexpr bool f64_acc_in_regs() {
   return N <= 20;
 }
 
+// Where the FP64 accumulator is a global buffer (24^3), its first elements of
+// each thread's line live in registers and the next ones in LDS (thread-private
+// slots beside the transpose array), which takes their read-modify-write off
+// device memory: the kernel there is bound by that traffic.
+template <int N>
+constexpr int f64_acc_regs() {
+  return f64_acc_in_regs<N>() ? 0 : 4;
+}
+template <int N>
+constexpr int f64_acc_lds() {
+  return f64_acc_in_regs<N>() ? 0 : 4;
+}
+
 // the target held in registers for the whole work item (see the FP32 kernel):
 // at 16^3 two 256-thread workgroups per CU leave room for it
 template <int N>
@@ -68,7 +81,8 @@ size_t fused64_acc_scratch_elems(int n, int nslots) {
 namespace {
 
 template <int N>
-__device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc_slot, c128* __restrict__ lds) {
+__device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc_slot, c128* __restrict__ lds,
+                                         c128* __restrict__ lds_acc) {
   constexpr int NTI = N * N;
   constexpr int NR = N * N * N;
   constexpr int NPH = f64_nph<N>();
@@ -77,6 +91,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
   constexpr int NBK = N / NPH;    // l1 values per round of the y<->z transpose
   constexpr bool ACCREG = f64_acc_in_regs<N>();
   constexpr bool XREG = f64_x_in_regs<N>();
+  constexpr int AR = f64_acc_regs<N>(), AL = f64_acc_lds<N>();  // accumulator elements in registers, in LDS
   constexpr int G = f64_grp<N>();
   static_assert(N % G == 0, "load groups must tile the line");
 
@@ -123,6 +138,7 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
   const rsrc_t rAcc = make_rsrc(ACCREG ? a.out : a.accs + (long)acc_slot * NR, ACCREG ? 0u : FB);
 
   c128 acc[ACCREG ? N : 1];
+  c128 accr[AR > 0 ? AR : 1];
   c128 xr[XREG ? N : 1];
   if constexpr (XREG) static_for<N>([&](auto m1) { xr[m1] = ld_c128(rX, voff, (unsigned)(decltype(m1)::value * NTI * 16)); });
   if constexpr (ACCREG) {
@@ -243,13 +259,21 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
         // the position of the pair in the (k', j) loop is uniform: one branch per pair
         const bool first = ks == 0 && j == 0;
         auto mac = [&](auto load_acc) {
-#pragma unroll
-          for (int m1 = 0; m1 < N; ++m1) {
+          constexpr bool LOAD = decltype(load_acc)::value;
+          static_for<N>([&](auto mm) {
+            constexpr int m1 = decltype(mm)::value;
             const unsigned so = (unsigned)(m1 * NTI * 16);
             c128 tot = cmul(ld_c128(rM, voff, so), v[m1]);
-            if constexpr (decltype(load_acc)::value) tot = ld_c128(rAcc, voff_t16, so) + tot;
-            st_c128(tot, rAcc, voff_t16, so);
-          }
+            if constexpr (m1 < AR) {
+              accr[m1] = LOAD ? accr[m1] + tot : tot;
+            } else if constexpr (m1 < AR + AL) {
+              c128& slot = lds_acc[(m1 - AR) * NTI + t];
+              slot = LOAD ? slot + tot : tot;
+            } else {
+              if constexpr (LOAD) tot = ld_c128(rAcc, voff_t16, so) + tot;
+              st_c128(tot, rAcc, voff_t16, so);
+            }
+          });
         };
         if (first) mac(std::false_type{});
         else mac(std::true_type{});
@@ -262,6 +286,8 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
     const unsigned so = (unsigned)(m1 * NTI * 16);
     c128 sum;
     if constexpr (ACCREG) sum = acc[m1];
+    else if (m1 < AR) sum = accr[m1 < AR ? m1 : 0];
+    else if (m1 < AR + AL) sum = lds_acc[(m1 - AR) * NTI + t];
     else sum = ld_c128(rAcc, voff_t16, so);
     c128 o = cscale(sum, a.scale);
     if (a.accumulate) o = ld_c128(rOut, voff, so) + o;
@@ -272,6 +298,8 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
 template <int N>
 __global__ void __launch_bounds__(N * N) fused64_apply_kernel(Fused64Args a) {
   __shared__ c128 lds[f64_lds_elems<N>()];
+  __shared__ c128 lds_acc[f64_acc_lds<N>() > 0 ? f64_acc_lds<N>() * N * N : 1];
+  static_assert((f64_lds_elems<N>() + f64_acc_lds<N>() * N * N) * 16 <= 160 * 1024, "LDS of the fused FP64 kernel");
   int b = blockIdx.x;
   if (a.xcd_map) {
     // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous run of targets
@@ -280,7 +308,7 @@ __global__ void __launch_bounds__(N * N) fused64_apply_kernel(Fused64Args a) {
     const int x = b % 8, r = b / 8;
     b = x * q + (x < rem ? x : rem) + r;
   }
-  f64_item<N>(a, a.item0 + b, blockIdx.x, lds);
+  f64_item<N>(a, a.item0 + b, blockIdx.x, lds, lds_acc);
 }
 
 template <int N>
