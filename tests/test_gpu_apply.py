@@ -214,3 +214,34 @@ def test_paper_screening_parameter(device, n, prec):
     assert rel_per_k(got, ref) < TOL[prec]
     # and the two screening values give different operators
     assert rel_per_k(oracle.fock_apply(u, u, kp, cell, OMEGA, rows=[(0, 0)])[:1, :1], ref[:1, :1]) > 1e-3
+
+
+def test_noncubic_fp32_other_calls(device):
+    """The FP32 form on a 16 x 20 x 24 grid through the other calls that reach the pair
+    sum: one k-point range (its rows of the full application, bit for bit), the batched
+    call with a cubic cell beside it (the cells run one after another), and a Taylor-4
+    step against the oracle's."""
+    print("[gpu] noncubic fp32: krange, batched, taylor", flush=True)
+    from oracle import taylor as otaylor
+    from paper_1507_05156_amd.api import Plan
+    cell = np.diag([10.26, 11.0, 12.5])
+    kp = synth.gamma_mesh(2, cell, 2, 1)
+    u = synth.orbitals((16, 20, 24), cell, kp, 2, seed=340)
+    d = to_dev(u)
+    plan = make_plan(cell, kp, 2, (16, 20, 24), "fp32")
+    full = plan.apply(d).cpu().numpy()
+    part = plan.apply_krange(d, 1, 2).cpu().numpy()
+    assert np.array_equal(part, full[1:3])
+    ccell = synth.cubic_cell()
+    ckp = synth.gamma_mesh(2, ccell, 1, 1)
+    cu = synth.orbitals(16, ccell, ckp, 3, seed=341)
+    both = Plan([dict(n=(16, 20, 24), a=cell, kpts=kp, nb=2, omega=OMEGA),
+                 dict(n=16, a=ccell, kpts=ckp, nb=3, omega=OMEGA)], prec="fp32")
+    outs = [o.cpu().numpy() for o in both.apply_batched([d, to_dev(cu)])]
+    assert np.array_equal(outs[0], full)
+    assert rel_per_k(outs[1], oracle.fock_apply(cu, cu, ckp, ccell, OMEGA)) < 1e-6
+    avec = np.array([0.0, 0.0, 0.03])
+    psi = d.clone()
+    plan.taylor_step(psi, avec, 0.02, 0.25)
+    ref = otaylor.step_matfree(u, kp, cell, OMEGA, avec, 0.02, 0.25)
+    assert rel_per_k(psi.cpu().numpy(), ref) < 1e-6
