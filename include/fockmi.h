@@ -98,6 +98,13 @@ fock_status fock_plan_destroy(fockmi_plan plan);
  *   phi   : device [nk][nphi][N_r] complex128 target fields (may equal u_occ)
  *   vphi  : device [nk][nphi][N_r] complex128 output, overwritten; must not
  *           overlap u_occ or phi
+ * With phi == u_occ on a 32^3 cell of at least 3 k-points (FOCK_FP32_COMP,
+ * no down-sampling) the pair kernel computes each pair of k-points once and
+ * adds its conjugate term to the other target through per-XCD mirror copies:
+ * the plan then holds 8 * nk * nb * N_r * 32 bytes of them (29 GB for
+ * 216 k-points and 16 bands). The result is bitwise repeatable and agrees
+ * with the form that runs every pair to rounding (FOCKMI_SPLIT_SYM=0 at plan
+ * creation selects that form).
  * Stream-ordered; returns without synchronising. */
 fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
                        void* vphi, void* stream);

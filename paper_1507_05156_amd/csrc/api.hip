@@ -203,6 +203,13 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   // the split 32^3 form runs one workgroup per CU, two per target (a multiple of 16)
   const int nwg_split = (num_cus / 16) * 16;
   const bool has_split = n == 32 && c.SD.ptr && nwg_split >= 16 && has_ls && !accumulate;
+  // its pair symmetry: u as targets and sources over the whole k mesh (W of source b on
+  // target a is conj of W of a on b); the mirror copies need 8 nitems nr (8 lanes + 16 + 8)
+  // bytes
+  const size_t mirror_bytes = (size_t)8 * nitems * nr * (sizeof(c64) * (1 + split32_mirror_lanes()) + sizeof(c128));
+  const bool sym = has_split && split_sym && !c.ds && ps.ntk == c.nk && ps.nsk == c.nk &&
+                   ps.qidx == (const int*)c.qidx.ptr && X == P && P == M && nx == ns && c.nk >= 3 &&
+                   (!workspace_cap || mirror_bytes <= workspace_cap);
   auto usable = [&](int v) {
     if (n != 32) return v >= 0 && v < fused_variants(n);
     return v == 0 || (v == 1 && has_ls) || (v == 2 && has_split);
@@ -264,6 +271,33 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
           FOCK_OK)
         return st2;
       if ((st2 = sstatus.ensure(sizeof(int), workspace_cap, "abort word")) != FOCK_OK) return st2;
+      if (sym) {
+        const size_t nel = (size_t)8 * nitems * nr;
+        if ((st2 = mpart.ensure(nel * split32_mirror_lanes() * sizeof(c64), workspace_cap, "mirror partial sums")) !=
+            FOCK_OK)
+          return st2;
+        if ((st2 = msum.ensure(nel * sizeof(c128), workspace_cap, "mirror FP64 sums")) != FOCK_OK) return st2;
+        if ((st2 = mcomp.ensure(nel * sizeof(c64), workspace_cap, "mirror compensation")) != FOCK_OK) return st2;
+        if ((st2 = mdone.ensure(split32_mirror_ctr_ints(nitems) * sizeof(int), workspace_cap, "mirror counters")) !=
+            FOCK_OK)
+          return st2;
+        if (sym_key[0] != nwg_split || sym_key[1] != c.nk || sym_key[2] != ns || sym_key[3] != split_stagger_shift) {
+          std::vector<int> rank, cnt;
+          split32_sym_tables(nwg_split, c.nk, ns, split_stagger_shift, &rank, &cnt);
+          if ((st2 = sym_rank.ensure(rank.size() * sizeof(int), workspace_cap, "mirror push order")) != FOCK_OK)
+            return st2;
+          if ((st2 = sym_cnt.ensure(cnt.size() * sizeof(int), workspace_cap, "mirror push counts")) != FOCK_OK)
+            return st2;
+          hipError_t e2 = hipMemcpy(sym_rank.ptr, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice);
+          if (e2 == hipSuccess)
+            e2 = hipMemcpy(sym_cnt.ptr, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice);
+          if (e2 != hipSuccess) return hip_fail(e2, "mirror tables");
+          sym_key[0] = nwg_split;
+          sym_key[1] = c.nk;
+          sym_key[2] = ns;
+          sym_key[3] = split_stagger_shift;
+        }
+      }
       if (!fallbacks.ptr) {
         if ((st2 = fallbacks.ensure(sizeof(long long), workspace_cap, "fallback count")) != FOCK_OK) return st2;
         hipError_t e2 = launch_zero_ll((long long*)fallbacks.ptr, st);
@@ -286,8 +320,24 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
     sa.flags = (int*)sflags.ptr;
     sa.status = (int*)sstatus.ptr;
     sa.wait_ticks = split_wait_ticks;
+    if (sym) {
+      sa.sym = 1;
+      sa.ndelta = c.nk / 2 + 1;
+      sa.npush = (c.nk - 1) / 2;
+      sa.stagger_shift = split_stagger_shift;
+      sa.rank = (const int*)sym_rank.ptr;
+      sa.mpart = (c64*)mpart.ptr;
+      sa.msum = (c128*)msum.ptr;
+      sa.mcomp = (c64*)mcomp.ptr;
+      sa.mdone = (int*)mdone.ptr;
+    }
     hipError_t e2 = launch_split32(sa, nwg_split, st);
     if (e2 != hipSuccess) return e2;
+    // the mirror copies into the output (skipped when the split launch stopped)
+    if (sym && (e2 = launch_split32_sym_combine(out, (const c128*)msum.ptr, (const c64*)mcomp.ptr,
+                                                (const c64*)mpart.ptr, (const int*)sym_cnt.ptr, nitems, scale,
+                                                (const int*)sstatus.ptr, st)) != hipSuccess)
+      return e2;
     // the lockstep form behind it, run only if the split launch stopped
     FusedArgs fb = a;
     fb.gate = (const int*)sstatus.ptr;
@@ -483,6 +533,8 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
   }
   if (const char* g = std::getenv("FOCKMI_GRAPH")) p->use_graph = std::atoi(g) != 0;
   if (const char* g = std::getenv("FOCKMI_SPLIT_WAIT_TICKS")) p->split_wait_ticks = std::atol(g);
+  if (const char* g = std::getenv("FOCKMI_SPLIT_SYM")) p->split_sym = std::atoi(g);
+  if (const char* g = std::getenv("FOCKMI_SPLIT_STAGGER_SHIFT")) p->split_stagger_shift = std::min(std::max(std::atoi(g), 0), 30);
   {
     hipDeviceProp_t prop;
     p->num_cus = hipGetDeviceProperties(&prop, p->device) == hipSuccess ? prop.multiProcessorCount : 256;

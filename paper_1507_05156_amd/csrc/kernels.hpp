@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <vector>
 
 #include "fft_reg.hpp"
 
@@ -99,12 +100,35 @@ struct SplitArgs {
   int* flags;           // split32_flag_ints(nwg) ints: rendezvous counters, then XCD ids
   int* status;          // [0] abort word, cleared by the launch
   long wait_ticks;      // bound of one rendezvous wait (100 MHz ticks); < 0 stops the launch at once
+  // Pair symmetry (sym = 1; the targets are the sources u over the whole k mesh, nx = nb):
+  // target (k, i) runs the source k-points k + d mod nk, d = 0 .. nk/2 (ndelta blocks of nb
+  // bands), and for 1 <= d <= npush = (nk - 1)/2 it also adds conj(W) u_(k,i) to the mirror
+  // copy of source (k + d, j): the term of target (k + d, j) from source (k, i).
+  int sym;
+  int ndelta, npush;
+  int stagger_shift;    // target (k, i) takes the bands of a source k-point in the order j = (i >> shift) + m mod nb
+  const int* rank;      // [nitems][ndelta * nb]: a push's place in its mirror copy's order
+  c64* mpart;           // [8][nitems][split32_mirror_lanes()][32768] FP32 partial sums of the mirror copies (one per XCD)
+  c128* msum;           // [8][nitems][32768] their FP64 running sums
+  c64* mcomp;           // [8][nitems][32768] and the Neumaier compensation, rounded to FP32
+  int* mdone;           // split32_mirror_ctr_ints(nitems) counters, cleared by the launch
 };
 size_t split32_flag_ints(int nwg);
 size_t split32_xbuf_elems(int nwg);   // c64 elements
 size_t split32_sd_floats(int nq);
+size_t split32_mirror_ctr_ints(int nitems);
+int split32_mirror_lanes();  // FP32 partial sums per mirror copy
+// The order of the pushes into every mirror copy (rank, [nitems][ndelta*nb], -1 where a
+// pair pushes nothing) and the pushes each copy receives (cnt, [8][nitems]), for nwg
+// workgroups, nk k-points and nb bands.
+void split32_sym_tables(int nwg, int nk, int nb, int shift, std::vector<int>* rank, std::vector<int>* cnt);
 hipError_t launch_build_sd32(float* SD, const double* K, int nq, hipStream_t st);
 hipError_t launch_split32(const SplitArgs& s, int nwg, hipStream_t st);
+// out[b] += the mirror copies of target b (FP64 sum + compensation + scale * FP32 partial,
+// copies in XCD order); does nothing when status[0] != 0
+hipError_t launch_split32_sym_combine(c128* out, const c128* msum, const c64* mcomp, const c64* mpart,
+                                      const int* cnt, int nitems, double scale, const int* status,
+                                      hipStream_t st);
 // count[0] += (status[0] != 0); p[0] = 0 (diagnostics of the split form's fallbacks)
 hipError_t launch_count_abort(long long* count, const int* status, hipStream_t st);
 hipError_t launch_zero_ll(long long* p, hipStream_t st);

@@ -216,7 +216,8 @@ void Plan::destroy() {
   }
   for (DevBuf* b : {&batch, &shadow_x, &shadow_p, &shadow_m, &comp, &accs, &vu, &partial, &dotres, &srcbuf, &srcout,
                     &psi0, &phiA, &phiB, &predb, &srcbuf2, &kin, &vxb, &lam, &lam2, &gtmp, &ftmp, &phis, &norms,
-                    &red6, &vloc_buf, &sync, &parts, &xbuf, &sflags, &sstatus, &fallbacks})
+                    &red6, &vloc_buf, &sync, &parts, &xbuf, &sflags, &sstatus, &fallbacks, &mpart, &msum, &mcomp,
+                    &mdone, &sym_rank, &sym_cnt})
     b->release();
   bstate.release();
   eig.release();

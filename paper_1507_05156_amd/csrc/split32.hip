@@ -49,6 +49,24 @@
 // XCD mismatch, the launch sets an abort word and every workgroup stops; the
 // host then runs the one-CU lockstep kernel, gated on that word, over the whole
 // application (it rewrites every output element).
+//
+// Pair symmetry (SYM). When the targets are the sources u over the whole k mesh,
+// the pair (target b, source a) has the pair density conj of that of (a, b) and
+// the kernel table at -q on the reflected grid (Nyquist planes averaged over both
+// signs), so its W is the conjugate of W(a, b). Target (k, i) then runs only the
+// source k-points k + d mod N_k, d = 0 .. N_k/2 (the bands of each in a staggered
+// order), and for 1 <= d <= (N_k - 1)/2 also adds conj(W) u_(k,i) into a mirror
+// copy of target (k + d, j): half the FFT work. Every XCD has its own copy of each
+// target (the XCDs' L2s are not coherent within a launch), written only by its
+// workgroups, which check at the start that they share one XCD. The pushes into a
+// copy follow an order fixed on the host (round, pair, CU pair: a push waits only
+// for pushes of smaller keys, so the order cannot deadlock); each push adds into
+// the copy's FP32 partial sum and folds one element pair of it into the copy's
+// FP64 sums with Neumaier compensation, so no FP32 partial covers more than 16
+// pushes. A combine kernel adds the copies to the output in XCD order: the result
+// is bitwise repeatable.
+#include <algorithm>
+
 #include "fused_common.hpp"
 
 namespace fockmi {
@@ -68,6 +86,16 @@ constexpr unsigned kPairBytes = kHalfElems * 8u;
 constexpr int kFoldW = 4;
 constexpr int kFoldSp = kFoldW / 2;
 static_assert(kFoldW == 2 || kFoldW == 4 || kFoldW == 8, "fold width");
+// pair symmetry: FP32 partial sums ("lanes") per mirror copy. The push of rank r adds into
+// lane r mod kLanes and waits for that lane's previous push only, so consecutive pushes
+// into a copy (made by different CU pairs one pair apart) need not wait for each other.
+// On C2 (timing copies with racy waits, 1, 2 and 4 pushes of slack): 1,842, 1,690 and
+// 1,598 ms per application.
+constexpr int kLanes = 1;
+static_assert(kLanes == 1 || kLanes == 2 || kLanes == 4 || kLanes == 8, "mirror lanes");
+// lane h folds the element pair (n + h 16 / kLanes) mod 16 at its n-th push; two folds of
+// one element pair (by any lanes) are then at least 15 ranks apart (16 with one lane)
+constexpr int kFoldGap = 15;
 
 // s + c += x with the rounding error of each addition carried in c (no contraction).
 __device__ __forceinline__ void neumaier2(double& s, double& c, double x) {
@@ -94,6 +122,7 @@ __device__ __forceinline__ c64& lds_far(c64* lds, unsigned base) {
 
 namespace {
 
+template <bool SYM>
 __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2)))
 split32_kernel(SplitArgs S) {
   constexpr int NN = kN * kN;
@@ -130,7 +159,7 @@ split32_kernel(SplitArgs S) {
   // the calling wave waits until the other half's counter k reaches n (bounded; the
   // loop runs on uniform values); returns 0 when the launch stops (timeout, another
   // pair stopped it, or the host asked)
-  auto wait_for = [&](int k, int n) -> int {
+  auto wait_on = [&](int* ctr, int n) -> int {
     if (S.wait_ticks < 0) {
       __hip_atomic_store(S.status, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return 0;
@@ -138,8 +167,37 @@ split32_kernel(SplitArgs S) {
     const unsigned long t0 = __builtin_amdgcn_s_memrealtime();
     for (;;) {
       const int got = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(theirs + k * kCtr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (got >= n) return 1;
+      const int st = __builtin_amdgcn_readfirstlane(__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (st != 0) return 0;
+      if ((long)(__builtin_amdgcn_s_memrealtime() - t0) > S.wait_ticks) {
+        __hip_atomic_store(S.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  };
+  auto wait_for = [&](int k, int n) -> int { return wait_on(theirs + k * kCtr, n); };
+  // the calling wave waits until ctr[h kCtr] >= need[h] for every lane h (bounded as above;
+  // the lanes' counters are read together)
+  auto wait_lanes = [&](int* ctr, const int (&need)[kLanes]) -> int {
+    if (S.wait_ticks < 0) {
+      __hip_atomic_store(S.status, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 0;
+    }
+    const unsigned long t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      int got[kLanes];
+      static_for<kLanes>([&](auto hh) {
+        got[decltype(hh)::value] = __hip_atomic_load(ctr + decltype(hh)::value * kCtr, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+      });
+      bool ok = true;
+      static_for<kLanes>([&](auto hh) {
+        ok = ok && __builtin_amdgcn_readfirstlane(got[decltype(hh)::value]) >= need[decltype(hh)::value];
+      });
+      if (ok) return 1;
       const int st = __builtin_amdgcn_readfirstlane(__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (st != 0) return 0;
       if ((long)(__builtin_amdgcn_s_memrealtime() - t0) > S.wait_ticks) {
@@ -163,6 +221,20 @@ split32_kernel(SplitArgs S) {
       if (xm != xo) {
         __hip_atomic_store(S.status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         go = 0;
+      }
+    }
+    if constexpr (SYM) {
+      // the mirror copies of class x are shared by every workgroup b = x mod 8 through one
+      // L2: each checks that it runs on the XCD of block x, the class's first workgroup (it
+      // has work whenever any workgroup of its class has)
+      if (go) go = wait_on(S.flags + (x * (W / 2) * 2) * kHalfBlock, 1);
+      if (go) {
+        const int xl = __hip_atomic_load(xcc + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int xm = __hip_atomic_load(xcc + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (xl != xm) {
+          __hip_atomic_store(S.status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          go = 0;
+        }
       }
     }
     sh_go = go;
@@ -189,16 +261,29 @@ split32_kernel(SplitArgs S) {
   // element (m1', s) of layout A sits at c NN + m1' 2NN + s NN/2 + t of its field;
   // byte offset of element E beyond t (8-byte elements)
   auto offA8 = [](auto e) constexpr { constexpr int E = decltype(e)::value; return (unsigned)(((E % 16) * 2 * NN + (E / 16) * NN / 2) * 8); };
-  const int npair_tg = nkp * nb;  // pairs of one target
+  const int npair_tg = SYM ? S.ndelta * nb : nkp * nb;  // pairs of one target
   for (int tg = first; tg < a.nitems; tg += npairs) {
-    const int kt = tg / a.nx;
+    const int kt = tg / a.nx, it = tg - kt * a.nx;
+    // source orbital of pair s: (k', j) = (s / nb, s mod nb); with the pair symmetry
+    // (k', j) = (kt + d mod nk, j) for s = d nb + j
+    auto source = [&](int s) -> int {
+      if constexpr (SYM) {
+        const int d = s / nb, m = s - d * nb;
+        const int ks = kt + d < nkp ? kt + d : kt + d - nkp;
+        const int i0 = it >> S.stagger_shift;
+        const int j = i0 + m < nb ? i0 + m : i0 + m - nb;
+        return ks * nb + j;
+      } else {
+        return s;
+      }
+    };
     const rsrc_t rX = make_rsrc(a.X + (long)tg * 2 * kHalfElems + c * NN, 2 * kHalfElems * 8u);
     const rsrc_t rOut = make_rsrc(a.out + (long)tg * 2 * kHalfElems + c * NN, 2 * kHalfElems * 16u);
     const rsrc_t rComp = make_rsrc(a.comp + (long)tg * 2 * kHalfElems + c * NN, 2 * kHalfElems * 8u);
     c64 X[32], acc[32], v[32];
     // this half of the target, and the pair density of the first pair
     {
-      const rsrc_t rP0 = make_rsrc(a.P + c * NN, 2 * kHalfElems * 8u);
+      const rsrc_t rP0 = make_rsrc(a.P + (long)source(0) * 2 * kHalfElems + c * NN, 2 * kHalfElems * 8u);
       static_for<32>([&](auto e) {
         X[decltype(e)::value] = ld_c64(rX, voff8, offA8(e));
         v[decltype(e)::value] = ld_c64(rP0, voff8, offA8(e));
@@ -209,12 +294,13 @@ split32_kernel(SplitArgs S) {
       });
     }
     for (int src = 0; src < npair_tg; ++src) {
-      const int ks = src / nb;
+      const int sb = source(src);  // source orbital (k', j) = (sb / nb, sb mod nb)
+      const int ks = sb / nb;
       const int qi = __builtin_amdgcn_readfirstlane(a.qidx[kt * a.nk + ks]);
       const rsrc_t rSD = make_rsrc(S.SD + (long)qi * kHalfElems * 2, kHalfElems * 8u);
-      const rsrc_t rM = make_rsrc(a.M + (long)src * 2 * kHalfElems + c * NN, 2 * kHalfElems * 8u);
+      const rsrc_t rM = make_rsrc(a.M + (long)sb * 2 * kHalfElems + c * NN, 2 * kHalfElems * 8u);
       const bool has_next = src + 1 < npair_tg;
-      const rsrc_t rPn = make_rsrc(a.P + (long)(has_next ? src + 1 : src) * 2 * kHalfElems + c * NN,
+      const rsrc_t rPn = make_rsrc(a.P + (long)source(has_next ? src + 1 : src) * 2 * kHalfElems + c * NN,
                                    2 * kHalfElems * 8u);
       // ---- layout A: 16-point DFTs along m1' of the pair density in v
       static_for<2>([&](auto g) {
@@ -333,6 +419,109 @@ split32_kernel(SplitArgs S) {
       const unsigned fo0 = (unsigned)((((kFoldW * f) % 16) * 2 * NN + ((kFoldW * f) / 16) * NN / 2) * 8);
       c128 fq[kFoldW];
       c64 fc[kFoldW];
+      // ---- pair symmetry: this pair's push into the mirror copy of source sb held for
+      // this XCD (x), in the order the rank table fixes. The push of rank r (lane
+      // r mod kLanes, its n-th push) waits for the lane's previous push, and for every push
+      // of rank <= r - kFoldGap (its fold into the FP64 sums follows the previous fold of
+      // the same elements, which is at least kFoldGap ranks earlier). Counters per lane,
+      // half and wave: a wave touches only its own elements of the copy.
+      const bool push = SYM && src >= nb && src / nb <= S.npush;
+      int rank = 0;
+      const long cp = SYM ? (long)x * a.nitems + sb : 0;  // mirror copy (XCD, target sb)
+      int* const mctr = SYM ? S.mdone + ((cp * 2 + c) * 8 + w) * kLanes * kCtr : nullptr;
+      if constexpr (SYM) {
+        if (push) {
+          rank = __builtin_amdgcn_readfirstlane(S.rank[(long)tg * npair_tg + src]);
+          if (rank > 0) {
+            const int lane = rank & (kLanes - 1);
+            int need[kLanes];
+            static_for<kLanes>([&](auto hh) {
+              constexpr int h = decltype(hh)::value;
+              const int before = rank - kFoldGap - h;  // pushes of lane h with rank <= r - kFoldGap
+              need[h] = h == lane ? rank / kLanes : (before >= 0 ? before / kLanes + 1 : 0);
+            });
+            if (!wait_lanes(mctr, need)) sh_stop = 1;
+            // the copy was last written by other CUs of this XCD: read it from L2
+            asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+          }
+        }
+      }
+      const int mlane = rank & (kLanes - 1), mn = rank / kLanes;
+      // ---- mirror pass (pair symmetry): the lane's FP32 partial sum += conj(W) X, the fold
+      // of one element pair of it into the copy's FP64 sums, and the publish, ahead of the
+      // multiply-accumulate, so that the copy's next push waits for this part only. One
+      // code path for every pair (branching between forms of these loops makes the
+      // allocator spill): the partial sum is read through a resource of size 0 at the lane's
+      // first push (loads return zero), and every resource has size 0 when the pair pushes
+      // nothing (stores are dropped). The n-th push of lane h folds the element pair
+      // (E0, E0 + 1), E0 = 2 g, g = (n + h 16 / kLanes) mod 16, so each element of a lane is
+      // folded at every 16th push into the lane.
+      if constexpr (SYM) {
+#pragma clang fp contract(off)
+        const int mg = (mn + mlane * (16 / kLanes)) & 15;
+        const unsigned fm0 = (unsigned)(((2 * (mg & 7)) * 2 * NN + (mg >> 3) * NN / 2) * 8);
+        // the FP64 sums of pair mg were written before iff its first fold (by any lane) came
+        // before this push
+        int first_fold = 1 << 30;
+        static_for<kLanes>([&](auto hh) {
+          constexpr int h = decltype(hh)::value;
+          const int r0 = kLanes * ((mg - h * (16 / kLanes)) & 15) + h;
+          first_fold = r0 < first_fold ? r0 : first_fold;
+        });
+        const bool prev = push && first_fold < rank;
+        const c64* mp_base = S.mpart + (cp * kLanes + mlane) * 2 * kHalfElems + c * NN;
+        const c128* ms_base = S.msum + cp * 2 * kHalfElems + c * NN;
+        const c64* mc_base = S.mcomp + cp * 2 * kHalfElems + c * NN;
+        const rsrc_t rMPl = make_rsrc(mp_base, push && mn > 0 ? 2 * kHalfElems * 8u : 0u);
+        const rsrc_t rMPs = make_rsrc(mp_base, push ? 2 * kHalfElems * 8u : 0u);
+        constexpr int GP = 8;
+        static_for<32 / GP>([&](auto g) {
+          constexpr int G0 = decltype(g)::value * GP;
+          c64 qv[GP];
+          static_for<GP>([&](auto e) {
+            constexpr auto E = std::integral_constant<int, G0 + decltype(e)::value>{};
+            qv[decltype(e)::value] = ld_c64(rMPl, voff8, offA8(E));
+          });
+          __builtin_amdgcn_sched_barrier(0);
+          static_for<GP>([&](auto e) {
+            constexpr auto E = std::integral_constant<int, G0 + decltype(e)::value>{};
+            const c64 wv = v[E], xv = X[E], q0 = qv[decltype(e)::value];
+            st_c64(c64{fmadd(wv.im, xv.im, fmadd(wv.re, xv.re, q0.re)), fmadd(-wv.im, xv.re, fmadd(wv.re, xv.im, q0.im))},
+                   rMPs, voff8, offA8(E));
+          });
+        });
+        // the folded pair's partial sums and FP64 values
+        c128 msq[2];
+        c64 mq[2], mcq[2];
+        {
+          const rsrc_t rMSl = make_rsrc(ms_base, prev ? 2 * kHalfElems * 16u : 0u);
+          const rsrc_t rMCl = make_rsrc(mc_base, prev ? 2 * kHalfElems * 8u : 0u);
+          static_for<2>([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            mq[k] = ld_c64(rMPs, voff8, fm0 + k * 2 * NN * 8);  // the partial sum this thread has just stored
+            msq[k] = ld_c128(rMSl, voff16, 2 * (fm0 + k * 2 * NN * 8));
+            mcq[k] = ld_c64(rMCl, voff8, fm0 + k * 2 * NN * 8);
+          });
+        }
+        const rsrc_t rMSs = make_rsrc(ms_base, push ? 2 * kHalfElems * 16u : 0u);
+        const rsrc_t rMCs = make_rsrc(mc_base, push ? 2 * kHalfElems * 8u : 0u);
+        static_for<2>([&](auto kk) {
+          constexpr int k = decltype(kk)::value;
+          const unsigned fo = fm0 + k * 2 * NN * 8;
+          double sr = msq[k].re, si = msq[k].im, cr = mcq[k].re, ci = mcq[k].im;
+          neumaier2(sr, cr, a.scale * (double)mq[k].re);
+          neumaier2(si, ci, a.scale * (double)mq[k].im);
+          st_c128(c128{sr, si}, rMSs, voff16, 2 * fo);
+          st_c64(c64{(float)cr, (float)ci}, rMCs, voff8, fo);
+          st_c64(c64{0.0f, 0.0f}, rMPs, voff8, fo);  // the pair's partial sum starts again
+        });
+        if (push) {
+          // every store of this push is in L2: publish it to the lane's next push
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          __hip_atomic_store(mctr + mlane * kCtr, mn + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      // ---- the multiply-accumulate acc += M W, and v = conj(P_next) X
       constexpr int GM = 8;
       static_for<32 / GM>([&](auto g) {
         constexpr int G0 = decltype(g)::value * GM;
@@ -350,7 +539,6 @@ split32_kernel(SplitArgs S) {
         });
       });
       if (fold) {
-#pragma clang fp contract(off)
         static_for<kFoldW>([&](auto kk) {
           constexpr int k = decltype(kk)::value;
           if (fold_prev) {
@@ -361,6 +549,9 @@ split32_kernel(SplitArgs S) {
             fc[k] = c64{0.0f, 0.0f};
           }
         });
+      }
+      if (fold) {
+#pragma clang fp contract(off)
         static_for<32 / kFoldW>([&](auto ff) {
           constexpr int F = decltype(ff)::value;
           if (f == F) {
@@ -410,10 +601,57 @@ split32_kernel(SplitArgs S) {
   }
 }
 
-// flags, XCD ids and the abort word to zero (a kernel, so that a captured graph holds no memset)
-__global__ void split_reset_kernel(int* flags, int nflags, int* status) {
+// flags, XCD ids, mirror counters and the abort word to zero (a kernel, so that a
+// captured graph holds no memset)
+__global__ void split_reset_kernel(int* flags, int nflags, int* mdone, long nmdone, int* status) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nflags; i += gridDim.x * blockDim.x) flags[i] = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nmdone; i += (long)gridDim.x * blockDim.x)
+    mdone[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = 0;
+}
+
+// out[b] += the mirror copies of target b, in XCD order. In a copy that took n pushes, lane
+// h took the pushes of rank h, h + kLanes, ... and folds the element pair g at its pushes
+// m with m = g - h 16 / kLanes mod 16: the FP64 sum and compensation hold every fold (and
+// exist iff the first fold of g by any lane came before rank n), each lane's FP32 partial
+// sum the lane's pushes after its last fold of g (every push, if none).
+__global__ void sym_combine_kernel(c128* __restrict__ out, const c128* __restrict__ msum,
+                                   const c64* __restrict__ mcomp, const c64* __restrict__ mpart,
+                                   const int* __restrict__ cnt, int nitems, double scale, const int* status) {
+  constexpr long NR = (long)kN * kN * kN;
+  if (status[0] != 0) return;  // the split launch stopped: the lockstep form rewrites out
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)nitems * NR) return;
+  const int tb = (int)(idx / NR);
+  const int e = (int)(idx % NR);
+  // layout A of the kernel: half c = m1 mod 2, element E = 16 s + m1' with m1' = m1 / 2,
+  // s = m2 / 16; the fold pair of E is E / 2
+  const int m1 = e >> 10, m2 = (e >> 5) & 31;
+  const int g = 8 * (m2 >> 4) + (m1 >> 2);
+  int first_fold = 1 << 30;
+  for (int h = 0; h < kLanes; ++h) {
+    const int r0 = kLanes * ((g - h * (16 / kLanes)) & 15) + h;
+    first_fold = r0 < first_fold ? r0 : first_fold;
+  }
+  double re = out[idx].re, im = out[idx].im;
+  for (int xc = 0; xc < 8; ++xc) {
+    const int n = cnt[(long)xc * nitems + tb];
+    if (n == 0) continue;
+    const long cpy = (long)xc * nitems + tb;
+    double sr = 0.0, si = 0.0;
+    if (first_fold < n) {
+      sr = msum[cpy * NR + e].re + (double)mcomp[cpy * NR + e].re;
+      si = msum[cpy * NR + e].im + (double)mcomp[cpy * NR + e].im;
+    }
+    for (int h = 0; h < kLanes && h < n; ++h) {
+      const c64 p = mpart[(cpy * kLanes + h) * NR + e];
+      sr += scale * (double)p.re;
+      si += scale * (double)p.im;
+    }
+    re += sr;
+    im += si;
+  }
+  out[idx] = c128{re, im};
 }
 
 // (S, D) table: for layout C element (l2 * 512 + t), t = 32 l1' + l3, from the
@@ -450,6 +688,32 @@ hipError_t launch_zero_ll(long long* p, hipStream_t st) {
 }
 
 size_t split32_flag_ints(int nwg) { return (size_t)(nwg / 2) * 2 * kHalfBlock + (size_t)nwg; }
+size_t split32_mirror_ctr_ints(int nitems) { return (size_t)8 * nitems * 2 * (kT / 64) * kLanes * kCtr; }
+int split32_mirror_lanes() { return kLanes; }
+
+void split32_sym_tables(int nwg, int nk, int nb, int shift, std::vector<int>* rank, std::vector<int>* cnt) {
+  // every CU pair runs its targets round by round and the pairs of a target in order; a
+  // push's key is (round, pair, CU pair within the XCD), and each copy (XCD, target) takes
+  // its pushes in key order. A push waits only for pushes of smaller keys (or for its own
+  // pair's exchange partner at the same key), so the order cannot deadlock.
+  const int npairs = nwg / 2, per_x = npairs / 8;
+  const int nitems = nk * nb, ndelta = nk / 2 + 1, npush = (nk - 1) / 2, ns = ndelta * nb;
+  rank->assign((size_t)nitems * ns, -1);
+  cnt->assign((size_t)8 * nitems, 0);
+  const int rounds = (nitems + npairs - 1) / npairs;
+  for (int r = 0; r < rounds; ++r)
+    for (int s = nb; s < ns; ++s) {
+      const int d = s / nb, j = s % nb;
+      if (d > npush) break;
+      for (int xc = 0; xc < 8; ++xc)
+        for (int pp = 0; pp < per_x; ++pp) {
+          const int tg = xc * per_x + pp + r * npairs;
+          if (tg >= nitems) continue;
+          const int b = ((tg / nb + d) % nk) * nb + (((tg % nb) >> shift) + j) % nb;
+          (*rank)[(size_t)tg * ns + s] = (*cnt)[(size_t)xc * nitems + b]++;
+        }
+    }
+}
 size_t split32_xbuf_elems(int nwg) { return (size_t)(nwg / 2) * 2 * kHalfElems; }
 size_t split32_sd_floats(int nq) { return (size_t)nq * kHalfElems * 2; }
 
@@ -466,11 +730,28 @@ hipError_t launch_build_sd32(float* SD, const double* K, int nq, hipStream_t st)
 
 hipError_t launch_split32(const SplitArgs& s, int nwg, hipStream_t st) {
   if (nwg < 16 || nwg % 16 != 0 || s.f.accumulate) return hipErrorInvalidValue;
+  if (s.sym && (s.f.nx != s.f.nb || s.f.nitems != s.f.nk * s.f.nb || s.ndelta != s.f.nk / 2 + 1 ||
+                s.npush != (s.f.nk - 1) / 2 || !s.rank || !s.mpart || !s.msum || !s.mcomp || !s.mdone))
+    return hipErrorInvalidValue;
   const int nflags = (int)split32_flag_ints(nwg);
-  hipLaunchKernelGGL(split_reset_kernel, dim3((nflags + 255) / 256), dim3(256), 0, st, s.flags, nflags, s.status);
+  const long nmdone = s.sym ? (long)split32_mirror_ctr_ints(s.f.nitems) : 0;
+  const long nreset = std::max<long>(nflags, nmdone);
+  const int rblocks = (int)std::min<long>((nreset + 255) / 256, 4096);
+  hipLaunchKernelGGL(split_reset_kernel, dim3(rblocks), dim3(256), 0, st, s.flags, nflags, s.mdone, nmdone,
+                     s.status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(split32_kernel, dim3(nwg), dim3(kT), 0, st, s);
+  if (s.sym) hipLaunchKernelGGL(split32_kernel<true>, dim3(nwg), dim3(kT), 0, st, s);
+  else hipLaunchKernelGGL(split32_kernel<false>, dim3(nwg), dim3(kT), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_split32_sym_combine(c128* out, const c128* msum, const c64* mcomp, const c64* mpart,
+                                      const int* cnt, int nitems, double scale, const int* status,
+                                      hipStream_t st) {
+  const long n = (long)nitems * kN * kN * kN;
+  hipLaunchKernelGGL(sym_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, msum, mcomp,
+                     mpart, cnt, nitems, scale, status);
   return hipGetLastError();
 }
 

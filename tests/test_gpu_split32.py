@@ -2,7 +2,13 @@
 one exchange per pair) through the C ABI: against the FP64 oracle, bitwise
 repeatability, more bands than one FP32 partial sum holds (two folds per k'), a
 target count that leaves most CU pairs idle, and its fallback (the host forces
-every rendezvous to stop; the lockstep form behind it then gives the result)."""
+every rendezvous to stop; the lockstep form behind it then gives the result).
+
+With u as targets and sources over a whole mesh of at least 3 k-points the form uses
+the pair symmetry (W of source b on target a is the conjugate of W of a on b): each
+target runs the source k-points k + d, d = 0 .. N_k/2, and pushes the mirror terms of
+d = 1 .. (N_k - 1)/2 into per-XCD copies of the other targets. Those cases are checked
+against the oracle and against the form that runs every pair (FOCKMI_SPLIT_SYM=0)."""
 
 import os
 
@@ -78,8 +84,12 @@ def test_split_fallback_when_forced(device):
 
 def test_split_several_rounds_phi_and_shard(device):
     """27 k x 10 bands = 270 targets on 128 CU pairs (two full rounds and a partial
-    one); separate targets phi (3 per k); one k-range shard, bitwise equal to the full
-    application's rows (each target's sum does not depend on the CU pair that runs it)."""
+    one), in the symmetric form (odd N_k: no antipodal block; mirror copies that take
+    more than 16 pushes, so their elements are folded more than once): sampled rows
+    against the oracle, every k against the form that runs every pair. Separate targets
+    phi (3 per k, no symmetry); one k-range shard (no symmetry either), bitwise equal to
+    the rows of the full application that runs every pair (each target's sum does not
+    depend on the CU pair that runs it)."""
     print("[gpu] split 32^3 rounds, phi, shard", flush=True)
     cell = synth.cubic_cell()
     kp = synth.gamma_mesh(3, cell)
@@ -94,8 +104,13 @@ def test_split_several_rounds_phi_and_shard(device):
         e = np.linalg.norm(full[k, i] - ref[k, i]) / np.linalg.norm(ref[k, i])
         print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
         assert e < 1e-6
+    every = plan32(kp, 10, cell, FOCKMI_SPLIT_SYM=0)
+    full_every = every.apply(d).cpu().numpy()
+    e = rel_per_k(full, full_every)
+    print(f"  symmetric vs every pair: max per-k rel {e:.3e}", flush=True)
+    assert e < 1e-6
     part = plan.apply_krange(d, 12, 5).cpu().numpy()
-    assert np.array_equal(part, full[12:17])
+    assert np.array_equal(part, full_every[12:17])
     phi = synth.random_fields((len(kp), 3, 32, 32, 32), seed=821)
     got = plan.apply(d, to_dev(phi)).cpu().numpy()
     ref = oracle.fock_apply(u, phi, kp, cell, OMEGA, rows=[(20, 2)])
@@ -154,6 +169,52 @@ def test_split_single_target_single_pair(device):
     plan.profile(True)
     got = plan.apply(to_dev(u)).cpu().numpy()
     assert plan.profile_fallbacks() == 0
+    plan.profile(False)
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    assert rel_per_k(got, ref) < 1e-6
+
+
+def test_split_pair_symmetry(device):
+    """u over a 2x2x2 mesh, 3 bands: the antipodal block d = 4 runs in both rows, the
+    blocks d = 1..3 once with their mirror terms pushed. Every row against the oracle,
+    bitwise repeatable, against the form that runs every pair, and the E_x gradient
+    (the same symmetric pair sum) against the oracle."""
+    print("[gpu] split 32^3 pair symmetry", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell)
+    u = synth.orbitals(32, cell, kp, 3, seed=860)
+    plan = plan32(kp, 3, cell)
+    plan.profile(True)
+    d = to_dev(u)
+    got = plan.apply(d).cpu().numpy()
+    again = plan.apply(d).cpu().numpy()
+    assert plan.profile_fallbacks() == 0
+    plan.profile(False)
+    assert np.array_equal(got, again)
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
+    e = rel_per_k(got, ref)
+    print(f"  per-k rel err {e:.3e}", flush=True)
+    assert e < 1e-6
+    every = plan32(kp, 3, cell, FOCKMI_SPLIT_SYM=0).apply(d).cpu().numpy()
+    assert rel_per_k(got, every) < 1e-6
+    ge = plan.energy_vjp(d, 1.0).cpu().numpy()
+    assert rel_per_k(ge, oracle.energy_grad(u, kp, cell, OMEGA)) < 1e-6
+
+
+@pytest.mark.parametrize("ticks", [-1, 1])
+def test_split_pair_symmetry_falls_back(device, ticks):
+    """The symmetric form stopped by the host (every wait stops at once) and by its own
+    one-tick wait limit (the waits of the exchange and of the mirror pushes time out
+    inside the kernel): the combine of the mirror copies is skipped and the lockstep
+    form computes the whole application."""
+    print(f"[gpu] split 32^3 pair symmetry fallback, ticks {ticks}", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(2, cell)
+    u = synth.orbitals(32, cell, kp, 2, seed=870)
+    plan = plan32(kp, 2, cell, FOCKMI_SPLIT_WAIT_TICKS=ticks)
+    plan.profile(True)
+    got = plan.apply(to_dev(u)).cpu().numpy()
+    assert plan.profile_fallbacks() == 1
     plan.profile(False)
     ref = oracle.fock_apply(u, u, kp, cell, OMEGA)
     assert rel_per_k(got, ref) < 1e-6
