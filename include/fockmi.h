@@ -120,7 +120,9 @@ fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void
  * 0 <= k0, k0 + nk_out <= nk (FOCK_ERR_ARG otherwise). Each target's sum is the
  * one fock_apply computes; the plain FP64 path and the grid forms of the fused
  * kernel give the same bits, the 32^3 lockstep form may group its FP64
- * additions differently. Stream-ordered. */
+ * additions differently, and fock_apply's pair-symmetric 32^3 form (phi ==
+ * u_occ) adds each target's terms in another order (a k-range runs every
+ * pair of its targets). Stream-ordered. */
 fock_status fock_apply_krange(fockmi_plan plan, int cell, const void* u_occ, int k0, int nk_out, const void* phi,
                               int nphi, void* vphi, void* stream);
 

@@ -45,9 +45,13 @@ def test_krange_rows_equal_the_full_application(device, prec):
 
 
 def test_krange_32cube(device):
-    """32^3 default form (the split form: each target's sum is independent of the
-    target count, so the rows are bitwise equal; the lockstep form's k' split may group
-    its FP64 additions differently): rows agree to rounding and with the oracle."""
+    """32^3 default form (the split form). A k-range runs every pair of its targets: its
+    rows equal those of the full application that runs every pair (FOCKMI_SPLIT_SYM=0;
+    each target's sum is independent of the target count) to 1e-13, and agree to FP32
+    rounding with the default full application, which uses the pair symmetry (u as
+    targets and sources: each pair of k-points once) and so sums each target's terms in
+    another order; and with the oracle."""
+    import os
     print("[gpu] krange 32^3", flush=True)
     cell = synth.cubic_cell()
     kp = synth.gamma_mesh(2, cell)
@@ -57,6 +61,14 @@ def test_krange_32cube(device):
     full = p.apply(ud).cpu().numpy()
     part = p.apply_krange(ud, 2, 3).cpu().numpy()
     rel = np.max(np.abs(part - full[2:5])) / np.max(np.abs(full[2:5]))
+    assert rel < 1e-6, rel
+    os.environ["FOCKMI_SPLIT_SYM"] = "0"
+    try:
+        every = plan(cell, kp, 2, 32, "fp32")
+    finally:
+        del os.environ["FOCKMI_SPLIT_SYM"]
+    full_every = every.apply(ud).cpu().numpy()
+    rel = np.max(np.abs(part - full_every[2:5])) / np.max(np.abs(full_every[2:5]))
     assert rel < 1e-13, rel
     ref = oracle.fock_apply(u, u, kp, cell, OMEGA, rows=[(4, 1)])
     e = np.linalg.norm(part[2, 1] - ref[4, 1]) / np.linalg.norm(ref[4, 1])
