@@ -4,7 +4,9 @@
 A step is one full application V_x[u] u over every (k, i, k', j) pair of the
 workload (kernel tables resident, orbitals already in HBM), in the fused FP32
 form (complex64 pair FFTs; FP32 partial sums over at most 16 bands, added into
-Neumaier-compensated FP64 sums; at 32^3 each target split over two CUs).
+Neumaier-compensated FP64 sums; at 32^3 each target split over two CUs, and,
+since the targets are the sources, each pair of k-points transformed once: the
+W of (k', j) on (k, i) is the conjugate of that of (k, i) on (k', j)).
 The plain FP64 path runs the same orbitals for the speed-up and the per-k
 error of the FP32 form; the FP64 oracle runs a bounded sample on the host.
 
@@ -33,9 +35,9 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
 # the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "731452f3d94203dce5adb4c2adab6d17d7330f338079e00fea7e11f7790a97f4",
+    "sources_sha256": "9168d67367a523917ef5e62ba4e32986fa0b78b5e4ac926d7a922e8216cf4ed2",
     "workload": 2,
-    "fetch_kib": 1873621141.4375, "write_kib": 3644336685.75,
+    "fetch_kib": 1571264130.3125, "write_kib": 3546868379.125,
     "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
 }
 # the sources of the dominant 32^3 kernel (split32_kernel) whose dispatches the counters measured
@@ -59,6 +61,15 @@ def counter_traffic(workload: int):
     if c["sources_sha256"] != kernel_sources_digest() or c["workload"] != workload or c["fetch_kib"] is None:
         return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
+
+def symmetric_pair_ffts(n: int, nk: int, nb: int) -> int | None:
+    """Pairs whose FFTs the 32^3 split kernel runs when it uses the pair symmetry
+    (u as targets and sources, at least 3 k-points): each target runs the source
+    k-points k + d, d = 0 .. nk/2. None when the kernel runs every pair."""
+    if n != 32 or nk < 3 or os.environ.get("FOCKMI_SPLIT_SYM", "1") == "0":
+        return None
+    return nk * nb * (nk // 2 + 1) * nb
 
 
 def flops_per_pair(nr: int) -> float:
@@ -446,6 +457,7 @@ def main():
     alg_bytes = pairs * nr * 8.0   # one complex64 orbital streamed per pair
     achieved_gbs = alg_bytes / kern_avg_s / 1e9
     traffic = counter_traffic(args.workload)
+    sym_pairs = symmetric_pair_ffts(n, nk, nb)
     print(f"[bench] fp32: {elapsed / args.steps * 1e3:.1f} ms/step, {value:.4e} pairs/s, "
           f"kernel {kern_avg_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
     e32 = plan32.energy(ud)
@@ -506,8 +518,11 @@ def main():
         "data": "synthetic seeded orbitals",
         "config": {"workload": f"{n}^3 grid, {round(nk ** (1 / 3))}^3 Gamma-centred k-mesh ({nk} k), {nb} bands, "
                                f"a=10.26 bohr cubic, omega={omega} bohr^-1",
-                   "pairs_per_step": pairs, "ffts_per_step": 2 * pairs,
-                   "kernel": "split FP32 pair kernel (each target on two CUs of one XCD)" if n == 32 else "fused FP32 pair kernel"},
+                   "pairs_per_step": pairs, "ffts_per_step": 2 * (sym_pairs or pairs),
+                   "pairs_transformed_per_step": sym_pairs or pairs,
+                   "kernel": ("split FP32 pair kernel (each target on two CUs of one XCD"
+                              + ("; pair symmetry: each pair of k-points transformed once)" if sym_pairs else ")"))
+                   if n == 32 else "fused FP32 pair kernel"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "split32_kernel" if n == 32 else f"fused_apply_kernel<{n}>", "kernel_ms_avg": kern_avg_s * 1e3, "launches": launches,
@@ -519,9 +534,13 @@ def main():
                      "valu_peak_unpacked_TFLOPs": FP32_VALU_PEAK_TFLOPS / 2,
                      "valu_frac_unpacked": achieved_tflops / (FP32_VALU_PEAK_TFLOPS / 2),
                      "flops_per_pair": flops_per_pair(nr),
+                     "valu_executed_TFLOPs": flops_per_pair(nr) * (sym_pairs or pairs) / kern_avg_s / 1e12,
+                     "note": ("achieved counts the application's algorithmic bytes, one complex64 orbital per "
+                              "(target, source) pair; with the pair symmetry the kernel transforms "
+                              f"{sym_pairs} of the {pairs} pairs" if sym_pairs else None),
                      "copy_GBs_measured": copy_gbs,
                      "frac_of_measured_copy": achieved_gbs / copy_gbs if copy_gbs else None},
-        "ffts_per_s": 2 * value,
+        "ffts_per_s": 2 * (sym_pairs or pairs) * args.steps / elapsed,
         "fp32_repeat_bitwise_equal": repeat_equal,
         "cpu_baseline": cpu,
     }
