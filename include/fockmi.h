@@ -103,8 +103,9 @@ fock_status fock_plan_destroy(fockmi_plan plan);
  * adds its conjugate term to the other target through per-XCD mirror copies:
  * the plan then holds 8 * nk * nb * N_r * 32 bytes of them (29 GB for
  * 216 k-points and 16 bands). The result is bitwise repeatable and agrees
- * with the form that runs every pair to rounding (FOCKMI_SPLIT_SYM=0 at plan
- * creation selects that form).
+ * with the form that runs every pair to rounding; that form runs instead
+ * when the copies exceed the plan's workspace cap or the free device memory,
+ * or with FOCKMI_SPLIT_SYM=0 at plan creation.
  * Stream-ordered; returns without synchronising. */
 fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void* phi, int nphi,
                        void* vphi, void* stream);

@@ -207,7 +207,7 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   // target a is conj of W of a on b); the mirror copies need 8 nitems nr (8 lanes + 16 + 8)
   // bytes
   const size_t mirror_bytes = (size_t)8 * nitems * nr * (sizeof(c64) * (1 + split32_mirror_lanes()) + sizeof(c128));
-  const bool sym = has_split && split_sym && !c.ds && ps.ntk == c.nk && ps.nsk == c.nk &&
+  bool sym = has_split && split_sym && !c.ds && ps.ntk == c.nk && ps.nsk == c.nk &&
                    ps.qidx == (const int*)c.qidx.ptr && X == P && P == M && nx == ns && c.nk >= 3 &&
                    (!workspace_cap || mirror_bytes <= workspace_cap);
   auto usable = [&](int v) {
@@ -272,15 +272,21 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
         return st2;
       if ((st2 = sstatus.ensure(sizeof(int), workspace_cap, "abort word")) != FOCK_OK) return st2;
       if (sym) {
+        // the mirror copies; when the device cannot hold them, the split form runs every pair
         const size_t nel = (size_t)8 * nitems * nr;
-        if ((st2 = mpart.ensure(nel * split32_mirror_lanes() * sizeof(c64), workspace_cap, "mirror partial sums")) !=
-            FOCK_OK)
-          return st2;
-        if ((st2 = msum.ensure(nel * sizeof(c128), workspace_cap, "mirror FP64 sums")) != FOCK_OK) return st2;
-        if ((st2 = mcomp.ensure(nel * sizeof(c64), workspace_cap, "mirror compensation")) != FOCK_OK) return st2;
-        if ((st2 = mdone.ensure(split32_mirror_ctr_ints(nitems) * sizeof(int), workspace_cap, "mirror counters")) !=
-            FOCK_OK)
-          return st2;
+        if (mpart.ensure(nel * split32_mirror_lanes() * sizeof(c64), workspace_cap, "mirror partial sums") !=
+                FOCK_OK ||
+            msum.ensure(nel * sizeof(c128), workspace_cap, "mirror FP64 sums") != FOCK_OK ||
+            mcomp.ensure(nel * sizeof(c64), workspace_cap, "mirror compensation") != FOCK_OK ||
+            mdone.ensure(split32_mirror_ctr_ints(nitems) * sizeof(int), workspace_cap, "mirror counters") != FOCK_OK) {
+          mpart.release();
+          msum.release();
+          mcomp.release();
+          mdone.release();
+          sym = false;
+        }
+      }
+      if (sym) {
         if (sym_key[0] != nwg_split || sym_key[1] != c.nk || sym_key[2] != ns || sym_key[3] != split_stagger_shift) {
           std::vector<int> rank, cnt;
           split32_sym_tables(nwg_split, c.nk, ns, split_stagger_shift, &rank, &cnt);

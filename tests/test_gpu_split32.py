@@ -177,8 +177,9 @@ def test_split_single_target_single_pair(device):
 def test_split_pair_symmetry(device):
     """u over a 2x2x2 mesh, 3 bands: the antipodal block d = 4 runs in both rows, the
     blocks d = 1..3 once with their mirror terms pushed. Every row against the oracle,
-    bitwise repeatable, against the form that runs every pair, and the E_x gradient
-    (the same symmetric pair sum) against the oracle."""
+    bitwise repeatable, against the form that runs every pair (also what a plan whose
+    workspace cap cannot hold the mirror copies runs), and the E_x gradient (the same
+    symmetric pair sum) against the oracle."""
     print("[gpu] split 32^3 pair symmetry", flush=True)
     cell = synth.cubic_cell()
     kp = synth.gamma_mesh(2, cell)
@@ -197,6 +198,10 @@ def test_split_pair_symmetry(device):
     assert e < 1e-6
     every = plan32(kp, 3, cell, FOCKMI_SPLIT_SYM=0).apply(d).cpu().numpy()
     assert rel_per_k(got, every) < 1e-6
+    # a workspace cap below the mirror copies (201 MB here) leaves the form that runs
+    # every pair, bit for bit
+    capped = plan32(kp, 3, cell, FOCKMI_WORKSPACE_CAP=100 << 20).apply(d).cpu().numpy()
+    assert np.array_equal(capped, every)
     ge = plan.energy_vjp(d, 1.0).cpu().numpy()
     assert rel_per_k(ge, oracle.energy_grad(u, kp, cell, OMEGA)) < 1e-6
 
