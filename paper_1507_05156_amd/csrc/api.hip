@@ -204,9 +204,8 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
   const int nwg_split = (num_cus / 16) * 16;
   const bool has_split = n == 32 && c.SD.ptr && nwg_split >= 16 && has_ls && !accumulate;
   // its pair symmetry: u as targets and sources over the whole k mesh (W of source b on
-  // target a is conj of W of a on b); the mirror copies need 8 nitems nr (8 lanes + 16 + 8)
-  // bytes
-  const size_t mirror_bytes = (size_t)8 * nitems * nr * (sizeof(c64) * (1 + split32_mirror_lanes()) + sizeof(c128));
+  // target a is conj of W of a on b); the mirror copies need 8 nitems nr (8 + 16 + 8) bytes
+  const size_t mirror_bytes = (size_t)8 * nitems * nr * (sizeof(c64) * 2 + sizeof(c128));
   bool sym = has_split && split_sym && !c.ds && ps.ntk == c.nk && ps.nsk == c.nk &&
                    ps.qidx == (const int*)c.qidx.ptr && X == P && P == M && nx == ns && c.nk >= 3 &&
                    (!workspace_cap || mirror_bytes <= workspace_cap);
@@ -274,8 +273,7 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
       if (sym) {
         // the mirror copies; when the device cannot hold them, the split form runs every pair
         const size_t nel = (size_t)8 * nitems * nr;
-        if (mpart.ensure(nel * split32_mirror_lanes() * sizeof(c64), workspace_cap, "mirror partial sums") !=
-                FOCK_OK ||
+        if (mpart.ensure(nel * sizeof(c64), workspace_cap, "mirror partial sums") != FOCK_OK ||
             msum.ensure(nel * sizeof(c128), workspace_cap, "mirror FP64 sums") != FOCK_OK ||
             mcomp.ensure(nel * sizeof(c64), workspace_cap, "mirror compensation") != FOCK_OK ||
             mdone.ensure(split32_mirror_ctr_ints(nitems) * sizeof(int), workspace_cap, "mirror counters") != FOCK_OK) {

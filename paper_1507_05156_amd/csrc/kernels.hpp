@@ -108,7 +108,7 @@ struct SplitArgs {
   int ndelta, npush;
   int stagger_shift;    // target (k, i) takes the bands of a source k-point in the order j = (i >> shift) + m mod nb
   const int* rank;      // [nitems][ndelta * nb]: a push's place in its mirror copy's order
-  c64* mpart;           // [8][nitems][split32_mirror_lanes()][32768] FP32 partial sums of the mirror copies (one per XCD)
+  c64* mpart;           // [8][nitems][32768] FP32 partial sums of the mirror copies (one per XCD)
   c128* msum;           // [8][nitems][32768] their FP64 running sums
   c64* mcomp;           // [8][nitems][32768] and the Neumaier compensation, rounded to FP32
   int* mdone;           // split32_mirror_ctr_ints(nitems) counters, cleared by the launch
@@ -117,7 +117,6 @@ size_t split32_flag_ints(int nwg);
 size_t split32_xbuf_elems(int nwg);   // c64 elements
 size_t split32_sd_floats(int nq);
 size_t split32_mirror_ctr_ints(int nitems);
-int split32_mirror_lanes();  // FP32 partial sums per mirror copy
 // The order of the pushes into every mirror copy (rank, [nitems][ndelta*nb], -1 where a
 // pair pushes nothing) and the pushes each copy receives (cnt, [8][nitems]), for nwg
 // workgroups, nk k-points and nb bands.

@@ -86,16 +86,6 @@ constexpr unsigned kPairBytes = kHalfElems * 8u;
 constexpr int kFoldW = 4;
 constexpr int kFoldSp = kFoldW / 2;
 static_assert(kFoldW == 2 || kFoldW == 4 || kFoldW == 8, "fold width");
-// pair symmetry: FP32 partial sums ("lanes") per mirror copy. The push of rank r adds into
-// lane r mod kLanes and waits for that lane's previous push only, so consecutive pushes
-// into a copy (made by different CU pairs one pair apart) need not wait for each other.
-// On C2 (timing copies with racy waits, 1, 2 and 4 pushes of slack): 1,842, 1,690 and
-// 1,598 ms per application.
-constexpr int kLanes = 1;
-static_assert(kLanes == 1 || kLanes == 2 || kLanes == 4 || kLanes == 8, "mirror lanes");
-// lane h folds the element pair (n + h 16 / kLanes) mod 16 at its n-th push; two folds of
-// one element pair (by any lanes) are then at least 15 ranks apart (16 with one lane)
-constexpr int kFoldGap = 15;
 
 // s + c += x with the rounding error of each addition carried in c (no contraction).
 __device__ __forceinline__ void neumaier2(double& s, double& c, double x) {
@@ -179,34 +169,6 @@ split32_kernel(SplitArgs S) {
     }
   };
   auto wait_for = [&](int k, int n) -> int { return wait_on(theirs + k * kCtr, n); };
-  // the calling wave waits until ctr[h kCtr] >= need[h] for every lane h (bounded as above;
-  // the lanes' counters are read together)
-  auto wait_lanes = [&](int* ctr, const int (&need)[kLanes]) -> int {
-    if (S.wait_ticks < 0) {
-      __hip_atomic_store(S.status, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return 0;
-    }
-    const unsigned long t0 = __builtin_amdgcn_s_memrealtime();
-    for (;;) {
-      int got[kLanes];
-      static_for<kLanes>([&](auto hh) {
-        got[decltype(hh)::value] = __hip_atomic_load(ctr + decltype(hh)::value * kCtr, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-      });
-      bool ok = true;
-      static_for<kLanes>([&](auto hh) {
-        ok = ok && __builtin_amdgcn_readfirstlane(got[decltype(hh)::value]) >= need[decltype(hh)::value];
-      });
-      if (ok) return 1;
-      const int st = __builtin_amdgcn_readfirstlane(__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      if (st != 0) return 0;
-      if ((long)(__builtin_amdgcn_s_memrealtime() - t0) > S.wait_ticks) {
-        __hip_atomic_store(S.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  };
 
   // start: the pair checks that both halves run on one XCD (they share its L2)
   if (t == 0) {
@@ -420,59 +382,40 @@ split32_kernel(SplitArgs S) {
       c128 fq[kFoldW];
       c64 fc[kFoldW];
       // ---- pair symmetry: this pair's push into the mirror copy of source sb held for
-      // this XCD (x), in the order the rank table fixes. The push of rank r (lane
-      // r mod kLanes, its n-th push) waits for the lane's previous push, and for every push
-      // of rank <= r - kFoldGap (its fold into the FP64 sums follows the previous fold of
-      // the same elements, which is at least kFoldGap ranks earlier). Counters per lane,
-      // half and wave: a wave touches only its own elements of the copy.
+      // this XCD (x), in the order the rank table fixes: the push of rank r waits until the
+      // copy has taken r pushes. The counters are per half and wave: a wave touches only
+      // its own elements of the copy.
       const bool push = SYM && src >= nb && src / nb <= S.npush;
       int rank = 0;
       const long cp = SYM ? (long)x * a.nitems + sb : 0;  // mirror copy (XCD, target sb)
-      int* const mctr = SYM ? S.mdone + ((cp * 2 + c) * 8 + w) * kLanes * kCtr : nullptr;
+      int* const mctr = SYM ? S.mdone + ((cp * 2 + c) * 8 + w) * kCtr : nullptr;
       if constexpr (SYM) {
         if (push) {
           rank = __builtin_amdgcn_readfirstlane(S.rank[(long)tg * npair_tg + src]);
           if (rank > 0) {
-            const int lane = rank & (kLanes - 1);
-            int need[kLanes];
-            static_for<kLanes>([&](auto hh) {
-              constexpr int h = decltype(hh)::value;
-              const int before = rank - kFoldGap - h;  // pushes of lane h with rank <= r - kFoldGap
-              need[h] = h == lane ? rank / kLanes : (before >= 0 ? before / kLanes + 1 : 0);
-            });
-            if (!wait_lanes(mctr, need)) sh_stop = 1;
-            // the copy was last written by other CUs of this XCD: read it from L2
+            if (!wait_on(mctr, rank)) sh_stop = 1;
+            // the copy was last written by another CU of this XCD: read it from L2
             asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
           }
         }
       }
-      const int mlane = rank & (kLanes - 1), mn = rank / kLanes;
-      // ---- mirror pass (pair symmetry): the lane's FP32 partial sum += conj(W) X, the fold
+      // ---- mirror pass (pair symmetry): the copy's FP32 partial sum += conj(W) X, the fold
       // of one element pair of it into the copy's FP64 sums, and the publish, ahead of the
       // multiply-accumulate, so that the copy's next push waits for this part only. One
       // code path for every pair (branching between forms of these loops makes the
-      // allocator spill): the partial sum is read through a resource of size 0 at the lane's
+      // allocator spill): the partial sum is read through a resource of size 0 at the copy's
       // first push (loads return zero), and every resource has size 0 when the pair pushes
-      // nothing (stores are dropped). The n-th push of lane h folds the element pair
-      // (E0, E0 + 1), E0 = 2 g, g = (n + h 16 / kLanes) mod 16, so each element of a lane is
-      // folded at every 16th push into the lane.
+      // nothing (stores are dropped). The push of rank r folds the element pair (E0, E0 + 1),
+      // E0 = 2 g, g = r mod 16, so each element of a copy is folded at every 16th push.
       if constexpr (SYM) {
 #pragma clang fp contract(off)
-        const int mg = (mn + mlane * (16 / kLanes)) & 15;
+        const int mg = rank & 15;
         const unsigned fm0 = (unsigned)(((2 * (mg & 7)) * 2 * NN + (mg >> 3) * NN / 2) * 8);
-        // the FP64 sums of pair mg were written before iff its first fold (by any lane) came
-        // before this push
-        int first_fold = 1 << 30;
-        static_for<kLanes>([&](auto hh) {
-          constexpr int h = decltype(hh)::value;
-          const int r0 = kLanes * ((mg - h * (16 / kLanes)) & 15) + h;
-          first_fold = r0 < first_fold ? r0 : first_fold;
-        });
-        const bool prev = push && first_fold < rank;
-        const c64* mp_base = S.mpart + (cp * kLanes + mlane) * 2 * kHalfElems + c * NN;
+        const bool prev = push && rank >= 16;  // the pair's FP64 sums were written before
+        const c64* mp_base = S.mpart + cp * 2 * kHalfElems + c * NN;
         const c128* ms_base = S.msum + cp * 2 * kHalfElems + c * NN;
         const c64* mc_base = S.mcomp + cp * 2 * kHalfElems + c * NN;
-        const rsrc_t rMPl = make_rsrc(mp_base, push && mn > 0 ? 2 * kHalfElems * 8u : 0u);
+        const rsrc_t rMPl = make_rsrc(mp_base, push && rank > 0 ? 2 * kHalfElems * 8u : 0u);
         const rsrc_t rMPs = make_rsrc(mp_base, push ? 2 * kHalfElems * 8u : 0u);
         constexpr int GP = 8;
         static_for<32 / GP>([&](auto g) {
@@ -516,9 +459,9 @@ split32_kernel(SplitArgs S) {
           st_c64(c64{0.0f, 0.0f}, rMPs, voff8, fo);  // the pair's partial sum starts again
         });
         if (push) {
-          // every store of this push is in L2: publish it to the lane's next push
+          // every store of this push is in L2: publish it to the copy's next push
           asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-          __hip_atomic_store(mctr + mlane * kCtr, mn + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(mctr, rank + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       // ---- the multiply-accumulate acc += M W, and v = conj(P_next) X
@@ -610,11 +553,10 @@ __global__ void split_reset_kernel(int* flags, int nflags, int* mdone, long nmdo
   if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = 0;
 }
 
-// out[b] += the mirror copies of target b, in XCD order. In a copy that took n pushes, lane
-// h took the pushes of rank h, h + kLanes, ... and folds the element pair g at its pushes
-// m with m = g - h 16 / kLanes mod 16: the FP64 sum and compensation hold every fold (and
-// exist iff the first fold of g by any lane came before rank n), each lane's FP32 partial
-// sum the lane's pushes after its last fold of g (every push, if none).
+// out[b] += the mirror copies of target b, in XCD order. In a copy that took n pushes,
+// the element pair g is folded at the pushes of rank g, g + 16, ... (so at least once iff
+// g < n): its FP64 sum and compensation hold the pushes up to its last fold, its FP32
+// partial sum the pushes after that.
 __global__ void sym_combine_kernel(c128* __restrict__ out, const c128* __restrict__ msum,
                                    const c64* __restrict__ mcomp, const c64* __restrict__ mpart,
                                    const int* __restrict__ cnt, int nitems, double scale, const int* status) {
@@ -628,26 +570,18 @@ __global__ void sym_combine_kernel(c128* __restrict__ out, const c128* __restric
   // s = m2 / 16; the fold pair of E is E / 2
   const int m1 = e >> 10, m2 = (e >> 5) & 31;
   const int g = 8 * (m2 >> 4) + (m1 >> 2);
-  int first_fold = 1 << 30;
-  for (int h = 0; h < kLanes; ++h) {
-    const int r0 = kLanes * ((g - h * (16 / kLanes)) & 15) + h;
-    first_fold = r0 < first_fold ? r0 : first_fold;
-  }
   double re = out[idx].re, im = out[idx].im;
   for (int xc = 0; xc < 8; ++xc) {
     const int n = cnt[(long)xc * nitems + tb];
     if (n == 0) continue;
-    const long cpy = (long)xc * nitems + tb;
+    const long o = ((long)xc * nitems + tb) * NR + e;
     double sr = 0.0, si = 0.0;
-    if (first_fold < n) {
-      sr = msum[cpy * NR + e].re + (double)mcomp[cpy * NR + e].re;
-      si = msum[cpy * NR + e].im + (double)mcomp[cpy * NR + e].im;
+    if (g < n) {
+      sr = msum[o].re + (double)mcomp[o].re;
+      si = msum[o].im + (double)mcomp[o].im;
     }
-    for (int h = 0; h < kLanes && h < n; ++h) {
-      const c64 p = mpart[(cpy * kLanes + h) * NR + e];
-      sr += scale * (double)p.re;
-      si += scale * (double)p.im;
-    }
+    sr += scale * (double)mpart[o].re;
+    si += scale * (double)mpart[o].im;
     re += sr;
     im += si;
   }
@@ -688,8 +622,7 @@ hipError_t launch_zero_ll(long long* p, hipStream_t st) {
 }
 
 size_t split32_flag_ints(int nwg) { return (size_t)(nwg / 2) * 2 * kHalfBlock + (size_t)nwg; }
-size_t split32_mirror_ctr_ints(int nitems) { return (size_t)8 * nitems * 2 * (kT / 64) * kLanes * kCtr; }
-int split32_mirror_lanes() { return kLanes; }
+size_t split32_mirror_ctr_ints(int nitems) { return (size_t)8 * nitems * 2 * (kT / 64) * kCtr; }
 
 void split32_sym_tables(int nwg, int nk, int nb, int shift, std::vector<int>* rank, std::vector<int>* cnt) {
   // every CU pair runs its targets round by round and the pairs of a target in order; a
