@@ -35,10 +35,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 # the same counter reads for a 1 GiB device copy in the same run. Valid only for
 # the kernel sources whose digest is recorded; a changed kernel reports null.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "9168d67367a523917ef5e62ba4e32986fa0b78b5e4ac926d7a922e8216cf4ed2",
+    "sources_sha256": "17366aee60d09d8aaf2b293d7cbb6ae6045b46719ecf4cfc199d1fe926a499ea",
     "workload": 2,
-    "fetch_kib": 1571264130.3125, "write_kib": 3546868379.125,
-    "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
+    "fetch_kib": 1539802589.625, "write_kib": 3537624652.5,
+    "fetch_scale": 1.999883181719894, "write_scale": 1.0,
 }
 # the sources of the dominant 32^3 kernel (split32_kernel) whose dispatches the counters measured
 KERNEL_SOURCES = ("paper_1507_05156_amd/csrc/split32.hip", "paper_1507_05156_amd/csrc/fft_reg.hpp",
