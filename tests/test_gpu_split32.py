@@ -249,3 +249,36 @@ def test_split_pair_symmetry_many_bands(device):
         e = np.linalg.norm(got[k, i] - ref[k, i]) / np.linalg.norm(ref[k, i])
         print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
         assert e < 1e-6
+
+
+
+@pytest.mark.parametrize("mesh", [2, 3])
+def test_split_pair_symmetry_16_bands(device, mesh):
+    """16 bands, u as targets and sources, so that the 16 CU pairs of an XCD hold the 16 bands
+    of one k-point (as on the 32^3 / 216 k / 16-band workload). 2x2x2 mesh: 128 targets, one
+    round; 3x3x3: 432 targets, four rounds, the last on three XCDs. Every k against the form
+    that runs every pair, bitwise repeatable, rows against the oracle."""
+    print(f"[gpu] split 32^3 pair symmetry, 16 bands, mesh {mesh}", flush=True)
+    cell = synth.cubic_cell()
+    kp = synth.gamma_mesh(mesh, cell)
+    u = synth.orbitals(32, cell, kp, 16, seed=890 + mesh)
+    plan = plan32(kp, 16, cell)
+    plan.profile(True)
+    d = to_dev(u)
+    got = plan.apply(d).cpu().numpy()
+    again = plan.apply(d).cpu().numpy()
+    assert plan.profile_fallbacks() == 0
+    plan.profile(False)
+    assert np.array_equal(got, again)
+    plan.close()
+    every = plan32(kp, 16, cell, FOCKMI_SPLIT_SYM=0).apply(d).cpu().numpy()
+    e = rel_per_k(got, every)
+    print(f"  symmetric vs every pair: max per-k rel {e:.3e}", flush=True)
+    assert e < 1e-6
+    nk = len(kp)
+    rows = [(0, 0), (nk // 2, 7), (nk - 1, 15)]
+    ref = oracle.fock_apply(u, u, kp, cell, OMEGA, rows=rows)
+    for k, i in rows:
+        e = np.linalg.norm(got[k, i] - ref[k, i]) / np.linalg.norm(ref[k, i])
+        print(f"  row {(k, i)}: rel err {e:.3e}", flush=True)
+        assert e < 1e-6
