@@ -258,21 +258,36 @@ __device__ __forceinline__ void f64_item(const Fused64Args& a, int item, int acc
       } else {
         // the position of the pair in the (k', j) loop is uniform: one branch per pair
         const bool first = ks == 0 && j == 0;
+        // in groups of GA elements, every load of a group issued before any of its stores: the
+        // compiler cannot tell the accumulator's stores from the multiplier's loads, so one
+        // element at a time would cost two memory round trips each
         auto mac = [&](auto load_acc) {
           constexpr bool LOAD = decltype(load_acc)::value;
-          static_for<N>([&](auto mm) {
-            constexpr int m1 = decltype(mm)::value;
-            const unsigned so = (unsigned)(m1 * NTI * 16);
-            c128 tot = cmul(ld_c128(rM, voff, so), v[m1]);
-            if constexpr (m1 < AR) {
-              accr[m1] = LOAD ? accr[m1] + tot : tot;
-            } else if constexpr (m1 < AR + AL) {
-              c128& slot = lds_acc[(m1 - AR) * NTI + t];
-              slot = LOAD ? slot + tot : tot;
-            } else {
-              if constexpr (LOAD) tot = ld_c128(rAcc, voff_t16, so) + tot;
-              st_c128(tot, rAcc, voff_t16, so);
-            }
+          constexpr int GA = 4;
+          static_assert(N % GA == 0, "accumulator groups");
+          static_for<N / GA>([&](auto gg) {
+            constexpr int C0 = decltype(gg)::value * GA;
+            c128 mv[GA], av[GA];
+            static_for<GA>([&](auto q) {
+              constexpr int m1 = C0 + decltype(q)::value;
+              mv[decltype(q)::value] = ld_c128(rM, voff, (unsigned)(m1 * NTI * 16));
+              if constexpr (LOAD && m1 >= AR + AL) av[decltype(q)::value] = ld_c128(rAcc, voff_t16, (unsigned)(m1 * NTI * 16));
+            });
+            __builtin_amdgcn_sched_barrier(0);
+            static_for<GA>([&](auto q) {
+              constexpr int m1 = C0 + decltype(q)::value;
+              const unsigned so = (unsigned)(m1 * NTI * 16);
+              c128 tot = cmul(mv[decltype(q)::value], v[m1]);
+              if constexpr (m1 < AR) {
+                accr[m1] = LOAD ? accr[m1] + tot : tot;
+              } else if constexpr (m1 < AR + AL) {
+                c128& slot = lds_acc[(m1 - AR) * NTI + t];
+                slot = LOAD ? slot + tot : tot;
+              } else {
+                if constexpr (LOAD) tot = av[decltype(q)::value] + tot;
+                st_c128(tot, rAcc, voff_t16, so);
+              }
+            });
           });
         };
         if (first) mac(std::false_type{});
