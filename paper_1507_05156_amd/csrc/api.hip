@@ -285,10 +285,9 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
         }
       }
       if (sym) {
-        if (sym_key[0] != nwg_split || sym_key[1] != c.nk || sym_key[2] != ns || sym_key[3] != split_stagger_shift ||
-            sym_key[4] != split_stagger_stride) {
+        if (sym_key[0] != nwg_split || sym_key[1] != c.nk || sym_key[2] != ns || sym_key[3] != split_stagger_shift) {
           std::vector<int> rank, cnt;
-          split32_sym_tables(nwg_split, c.nk, ns, split_stagger_shift, split_stagger_stride, &rank, &cnt);
+          split32_sym_tables(nwg_split, c.nk, ns, split_stagger_shift, &rank, &cnt);
           if ((st2 = sym_rank.ensure(rank.size() * sizeof(int), workspace_cap, "mirror push order")) != FOCK_OK)
             return st2;
           if ((st2 = sym_cnt.ensure(cnt.size() * sizeof(int), workspace_cap, "mirror push counts")) != FOCK_OK)
@@ -301,7 +300,6 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
           sym_key[1] = c.nk;
           sym_key[2] = ns;
           sym_key[3] = split_stagger_shift;
-          sym_key[4] = split_stagger_stride;
         }
       }
       if (!fallbacks.ptr) {
@@ -331,7 +329,6 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
       sa.ndelta = c.nk / 2 + 1;
       sa.npush = (c.nk - 1) / 2;
       sa.stagger_shift = split_stagger_shift;
-      sa.stagger_stride = split_stagger_stride;
       sa.rank = (const int*)sym_rank.ptr;
       sa.mpart = (c64*)mpart.ptr;
       sa.msum = (c128*)msum.ptr;
@@ -542,8 +539,6 @@ fock_status fock_plan_create(const fock_cell_desc* cells, int ncells, fock_prec 
   if (const char* g = std::getenv("FOCKMI_SPLIT_WAIT_TICKS")) p->split_wait_ticks = std::atol(g);
   if (const char* g = std::getenv("FOCKMI_SPLIT_SYM")) p->split_sym = std::atoi(g);
   if (const char* g = std::getenv("FOCKMI_SPLIT_STAGGER_SHIFT")) p->split_stagger_shift = std::min(std::max(std::atoi(g), 0), 30);
-  if (const char* g = std::getenv("FOCKMI_SPLIT_STAGGER_STRIDE"))
-    p->split_stagger_stride = std::min(std::max(std::atoi(g), 1), 1 << 20);
   {
     hipDeviceProp_t prop;
     p->num_cus = hipGetDeviceProperties(&prop, p->device) == hipSuccess ? prop.multiProcessorCount : 256;

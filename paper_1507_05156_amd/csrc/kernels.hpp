@@ -106,8 +106,7 @@ struct SplitArgs {
   // copy of source (k + d, j): the term of target (k + d, j) from source (k, i).
   int sym;
   int ndelta, npush;
-  int stagger_shift;    // target (k, i) takes the bands of a source k-point in the order
-  int stagger_stride;   // j = ((i >> shift) * stride + m) mod nb, m = 0 .. nb - 1
+  int stagger_shift;    // target (k, i) takes the bands of a source k-point in the order j = (i >> shift) + m mod nb
   const int* rank;      // [nitems][ndelta * nb]: a push's place in its mirror copy's order
   c64* mpart;           // [8][nitems][32768] FP32 partial sums of the mirror copies (one per XCD)
   c128* msum;           // [8][nitems][32768] their FP64 running sums
@@ -120,9 +119,8 @@ size_t split32_sd_floats(int nq);
 size_t split32_mirror_ctr_ints(int nitems);
 // The order of the pushes into every mirror copy (rank, [nitems][ndelta*nb], -1 where a
 // pair pushes nothing) and the pushes each copy receives (cnt, [8][nitems]), for nwg
-// workgroups, nk k-points, nb bands and the band order (shift, stride) of SplitArgs.
-void split32_sym_tables(int nwg, int nk, int nb, int shift, int stride, std::vector<int>* rank,
-                        std::vector<int>* cnt);
+// workgroups, nk k-points and nb bands.
+void split32_sym_tables(int nwg, int nk, int nb, int shift, std::vector<int>* rank, std::vector<int>* cnt);
 hipError_t launch_build_sd32(float* SD, const double* K, int nq, hipStream_t st);
 hipError_t launch_split32(const SplitArgs& s, int nwg, hipStream_t st);
 // out[b] += the mirror copies of target b (FP64 sum + compensation + scale * FP32 partial,

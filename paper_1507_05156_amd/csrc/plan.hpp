@@ -119,11 +119,10 @@ struct Plan {
   DevBuf fallbacks;                         // split launches that fell back (counted while profiling)
   long split_wait_ticks = 5000000;          // rendezvous bound of the split form, 50 ms (FOCKMI_SPLIT_WAIT_TICKS)
   // pair symmetry of the split form: mirror copies (FP32 partial, FP64 sum, compensation),
-  // their push counters, and the push order and counts for (nwg, nk, nb, shift, stride) = sym_key
+  // their push counters, and the push order and counts for (nwg, nk, nb) = sym_key
   DevBuf mpart, msum, mcomp, mdone, sym_rank, sym_cnt;
-  int sym_key[5] = {-1, -1, -1, -1, -1};
-  int split_stagger_shift = 1;              // the bands' order of the symmetric form (FOCKMI_SPLIT_STAGGER_SHIFT,
-  int split_stagger_stride = 1;             // FOCKMI_SPLIT_STAGGER_STRIDE)
+  int sym_key[4] = {-1, -1, -1, -1};
+  int split_stagger_shift = 1;              // the bands' order of the symmetric form (FOCKMI_SPLIT_STAGGER_SHIFT)
   int split_sym = 1;                        // 0: the split form runs every pair (FOCKMI_SPLIT_SYM=0)
   std::vector<double> host_norms;
   double* host_pinned = nullptr;            // 4 doubles for reductions

@@ -228,12 +228,11 @@ split32_kernel(SplitArgs S) {
     const int kt = tg / a.nx, it = tg - kt * a.nx;
     // source orbital of pair s: (k', j) = (s / nb, s mod nb); with the pair symmetry
     // (k', j) = (kt + d mod nk, j) for s = d nb + j
-    // band offset of this target in the symmetric order: ((i >> shift) * stride) mod nb
-    const int i0 = SYM ? (int)(((long)(it >> S.stagger_shift) * S.stagger_stride) % nb) : 0;
     auto source = [&](int s) -> int {
       if constexpr (SYM) {
         const int d = s / nb, m = s - d * nb;
         const int ks = kt + d < nkp ? kt + d : kt + d - nkp;
+        const int i0 = it >> S.stagger_shift;
         const int j = i0 + m < nb ? i0 + m : i0 + m - nb;
         return ks * nb + j;
       } else {
@@ -625,8 +624,7 @@ hipError_t launch_zero_ll(long long* p, hipStream_t st) {
 size_t split32_flag_ints(int nwg) { return (size_t)(nwg / 2) * 2 * kHalfBlock + (size_t)nwg; }
 size_t split32_mirror_ctr_ints(int nitems) { return (size_t)8 * nitems * 2 * (kT / 64) * kCtr; }
 
-void split32_sym_tables(int nwg, int nk, int nb, int shift, int stride, std::vector<int>* rank,
-                        std::vector<int>* cnt) {
+void split32_sym_tables(int nwg, int nk, int nb, int shift, std::vector<int>* rank, std::vector<int>* cnt) {
   // every CU pair runs its targets round by round and the pairs of a target in order; a
   // push's key is (round, pair, CU pair within the XCD), and each copy (XCD, target) takes
   // its pushes in key order. A push waits only for pushes of smaller keys (or for its own
@@ -644,8 +642,7 @@ void split32_sym_tables(int nwg, int nk, int nb, int shift, int stride, std::vec
         for (int pp = 0; pp < per_x; ++pp) {
           const int tg = xc * per_x + pp + r * npairs;
           if (tg >= nitems) continue;
-          const int off = (int)(((long)((tg % nb) >> shift) * stride) % nb);
-          const int b = ((tg / nb + d) % nk) * nb + (off + j) % nb;
+          const int b = ((tg / nb + d) % nk) * nb + (((tg % nb) >> shift) + j) % nb;
           (*rank)[(size_t)tg * ns + s] = (*cnt)[(size_t)xc * nitems + b]++;
         }
     }
@@ -667,7 +664,6 @@ hipError_t launch_build_sd32(float* SD, const double* K, int nq, hipStream_t st)
 hipError_t launch_split32(const SplitArgs& s, int nwg, hipStream_t st) {
   if (nwg < 16 || nwg % 16 != 0 || s.f.accumulate) return hipErrorInvalidValue;
   if (s.sym && (s.f.nx != s.f.nb || s.f.nitems != s.f.nk * s.f.nb || s.ndelta != s.f.nk / 2 + 1 ||
-                s.stagger_shift < 0 || s.stagger_shift > 30 || s.stagger_stride < 1 ||
                 s.npush != (s.f.nk - 1) / 2 || !s.rank || !s.mpart || !s.msum || !s.mcomp || !s.mdone))
     return hipErrorInvalidValue;
   const int nflags = (int)split32_flag_ints(nwg);

@@ -5,8 +5,7 @@ against the library's own table builder: every ordered (target, source) pair
 covered exactly once, each mirror copy's ranks in the key order that keeps the
 kernel's waits free of deadlock, and the push counts. Configurations: the 32^3 /
 216 k / 16-band workload, even and odd k counts, fewer targets than CU pairs, more
-bands than 16, other workgroup counts, and twelve band orders (four shifts by three
-strides)."""
+bands than 16, other workgroup counts, and four band orders."""
 
 import os
 import shutil
@@ -29,12 +28,12 @@ def test_symmetric_schedule(tmp_path):
                     "-L", LIBDIR, "-lfockmi", f"-Wl,-rpath,{LIBDIR}", "-o", exe], check=True)
     run = subprocess.run([exe], capture_output=True, text=True)
     lines = [l.split() for l in run.stdout.strip().split("\n")]
-    assert len(lines) == 9 * 4 * 3, run.stdout
-    for nwg, nk, nb, shift, stride, pairs, pushes, faults in lines:
-        assert int(faults) == 0, (nwg, nk, nb, shift, stride)
+    assert len(lines) == 9 * 4, run.stdout
+    for nwg, nk, nb, shift, pairs, pushes, faults in lines:
+        assert int(faults) == 0, (nwg, nk, nb, shift)
         nk, nb = int(nk), int(nb)
         # own pairs + pushes = every ordered pair of the application
         assert int(pairs) + int(pushes) == (nk * nb) ** 2
     assert run.returncode == 0
-    big = [l for l in lines if l[1] == "216" and l[3] == "1" and l[4] == "1"][0]
-    assert int(big[5]) == 6027264 and int(big[6]) == 5916672
+    big = [l for l in lines if l[1] == "216" and l[3] == "1"][0]
+    assert int(big[4]) == 6027264 and int(big[5]) == 5916672
