@@ -98,6 +98,9 @@ fock_status fock_plan_destroy(fockmi_plan plan);
  *   phi   : device [nk][nphi][N_r] complex128 target fields (may equal u_occ)
  *   vphi  : device [nk][nphi][N_r] complex128 output, overwritten; must not
  *           overlap u_occ or phi
+ * nphi >= 1: an empty target set is FOCK_ERR_ARG, as are a NULL or misaligned
+ * pointer, a cell index out of range and an output that overlaps an input;
+ * nothing is launched then.
  * With phi == u_occ on a 32^3 cell of at least 3 k-points (FOCK_FP32_COMP,
  * no down-sampling) the pair kernel computes each pair of k-points once and
  * adds its conjugate term to the other target through per-XCD mirror copies:
@@ -118,7 +121,7 @@ fock_status fock_apply(fockmi_plan plan, int cell, const void* u_occ, const void
  *   phi   : device [nk_out][nphi][N_r] complex128, the targets at k0 .. k0 + nk_out - 1
  *   vphi  : device [nk_out][nphi][N_r] complex128 output, overwritten; must not overlap
  *           u_occ or phi
- * 0 <= k0, k0 + nk_out <= nk (FOCK_ERR_ARG otherwise). Each target's sum is the
+ * 0 <= k0, nk_out >= 1, k0 + nk_out <= nk and nphi >= 1 (FOCK_ERR_ARG otherwise). Each target's sum is the
  * one fock_apply computes; the plain FP64 path and the grid forms of the fused
  * kernel give the same bits, the 32^3 lockstep form may group its FP64
  * additions differently, and fock_apply's pair-symmetric 32^3 form (phi ==

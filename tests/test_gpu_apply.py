@@ -179,6 +179,16 @@ def test_plan_errors_on_device(device):
     st = lib.fock_apply(plan._h, 0, C.c_void_p(ud.data_ptr()), C.c_void_p(ud.data_ptr()), 4,
                         C.c_void_p(ud.data_ptr()), None)
     assert st == -1 and b"overlaps" in lib.fock_last_error()
+    # an empty target set is an argument error, for the whole mesh and for a k-range
+    st = lib.fock_apply(plan._h, 0, C.c_void_p(ud.data_ptr()), C.c_void_p(ud.data_ptr()), 0,
+                        C.c_void_p(out.data_ptr()), None)
+    assert st == -1 and b"nphi" in lib.fock_last_error()
+    st = lib.fock_apply_krange(plan._h, 0, C.c_void_p(ud.data_ptr()), 0, 1, C.c_void_p(ud.data_ptr()), 0,
+                               C.c_void_p(out.data_ptr()), None)
+    assert st == -1 and b"nphi" in lib.fock_last_error()
+    st = lib.fock_apply_krange(plan._h, 0, C.c_void_p(ud.data_ptr()), 0, 0, C.c_void_p(ud.data_ptr()), 4,
+                               C.c_void_p(out.data_ptr()), None)
+    assert st == -1 and b"k-range" in lib.fock_last_error()
     with pytest.raises(FockError):
         from paper_1507_05156_amd.api import Plan
         Plan(dict(n=16, a=cell, kpts=np.vstack([kp, kp[:1]]), nb=4, omega=OMEGA))
