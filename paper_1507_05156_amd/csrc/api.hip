@@ -282,6 +282,7 @@ fock_status Plan::run_fused(Cell& c, const PairSet& ps, const c128* X, int nx, c
           mcomp.release();
           mdone.release();
           sym = false;
+          g_last_error.clear();  // the call goes on and succeeds: no failure to report
         }
       }
       if (sym) {
