@@ -42,7 +42,7 @@
 // exchange is a rendezvous of wave w of one half with wave w of the other through
 // counters in memory (thread t reads exactly what thread t of the other half
 // wrote): the writer waits for its stores, then publishes the pair number; the
-// reader polls it, invalidates its L1 and reads the other half from L2. Each half
+// reader polls it and reads the other half with device-coherent loads (below). Each half
 // has one mailbox; a wave rewrites it only after the other half's wave has
 // published that it read the previous contents. Every wait is bounded by a
 // real-time limit: on a timeout, or on an
@@ -65,6 +65,15 @@
 // FP64 sums with Neumaier compensation, so no FP32 partial covers more than 16
 // pushes. A combine kernel adds the copies to the output in XCD order: the result
 // is bitwise repeatable.
+//
+// Data that another CU wrote during the launch (the other half's mailbox, a mirror
+// copy's sums) is read with device-scope coherent loads (the SC1 cache policy), which
+// never return a line of this CU's L1 that those stores have made stale. An L1
+// invalidate at workgroup scope (buffer_inv sc0) does not give that: a timing copy
+// that touched a copy's lines a few microseconds before the other CU pair rewrote
+// them read the stale lines after its wait and gave wrong sums. A device-scope
+// invalidate (buffer_inv sc1) after every wait gave the right sums but took 2.19 s
+// per application on the 32^3 / 216 k / 16-band workload, against 1.82 s.
 #include <algorithm>
 
 #include "fused_common.hpp"
@@ -86,6 +95,16 @@ constexpr unsigned kPairBytes = kHalfElems * 8u;
 constexpr int kFoldW = 4;
 constexpr int kFoldSp = kFoldW / 2;
 static_assert(kFoldW == 2 || kFoldW == 4 || kFoldW == 8, "fold width");
+
+// Loads at device scope (cache policy SC1) of data another CU of the XCD has stored:
+// they read L2, never a stale line of this CU's L1.
+constexpr int kDeviceCoherent = 16;
+__device__ __forceinline__ c64 ld_c64_dev(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(c64, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kDeviceCoherent));
+}
+__device__ __forceinline__ c128 ld_c128_dev(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(c128, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kDeviceCoherent));
+}
 
 // s + c += x with the rounding error of each addition carried in c (no contraction).
 __device__ __forceinline__ void neumaier2(double& s, double& c, double x) {
@@ -312,8 +331,9 @@ split32_kernel(SplitArgs S) {
       // live ranges of the resident field across a divergent region)
       __hip_atomic_store(mine + (1 + 2 * w) * kCtr, npub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (!wait_for(1 + 2 * w, npub)) sh_stop = 1;
-      // the other half's data is read from L2, not from stale lines of this CU's L1
-      asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+      // no load of the other half's data moves above the wait (those loads are
+      // device-coherent)
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __builtin_amdgcn_sched_barrier(0);
       // ---- combine: G_c = S own + D (tau_c other), group by group
       static_for<32 / GC>([&](auto g) {
@@ -321,7 +341,7 @@ split32_kernel(SplitArgs S) {
         c64 o[GC], sd[GC];
         static_for<GC>([&](auto e) {
           constexpr int E = G0 + decltype(e)::value;
-          o[decltype(e)::value] = ld_c64(rTheirs, voff8, (unsigned)(E * kT * 8));
+          o[decltype(e)::value] = ld_c64_dev(rTheirs, voff8, (unsigned)(E * kT * 8));
           if constexpr (G0 == 0) sd[decltype(e)::value] = sd0[decltype(e)::value];
           else sd[decltype(e)::value] = ld_c64(rSD, voff8, (unsigned)(E * kT * 8));
         });
@@ -394,8 +414,9 @@ split32_kernel(SplitArgs S) {
           rank = __builtin_amdgcn_readfirstlane(S.rank[(long)tg * npair_tg + src]);
           if (rank > 0) {
             if (!wait_on(mctr, rank)) sh_stop = 1;
-            // the copy was last written by another CU of this XCD: read it from L2
-            asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+            // the copy was last written by another CU of this XCD: its loads below are
+            // device-coherent and stay below the wait
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
           }
         }
       }
@@ -423,7 +444,7 @@ split32_kernel(SplitArgs S) {
           c64 qv[GP];
           static_for<GP>([&](auto e) {
             constexpr auto E = std::integral_constant<int, G0 + decltype(e)::value>{};
-            qv[decltype(e)::value] = ld_c64(rMPl, voff8, offA8(E));
+            qv[decltype(e)::value] = ld_c64_dev(rMPl, voff8, offA8(E));
           });
           __builtin_amdgcn_sched_barrier(0);
           static_for<GP>([&](auto e) {
@@ -441,9 +462,9 @@ split32_kernel(SplitArgs S) {
           const rsrc_t rMCl = make_rsrc(mc_base, prev ? 2 * kHalfElems * 8u : 0u);
           static_for<2>([&](auto kk) {
             constexpr int k = decltype(kk)::value;
-            mq[k] = ld_c64(rMPs, voff8, fm0 + k * 2 * NN * 8);  // the partial sum this thread has just stored
-            msq[k] = ld_c128(rMSl, voff16, 2 * (fm0 + k * 2 * NN * 8));
-            mcq[k] = ld_c64(rMCl, voff8, fm0 + k * 2 * NN * 8);
+            mq[k] = ld_c64_dev(rMPs, voff8, fm0 + k * 2 * NN * 8);  // the partial sum this thread has just stored
+            msq[k] = ld_c128_dev(rMSl, voff16, 2 * (fm0 + k * 2 * NN * 8));
+            mcq[k] = ld_c64_dev(rMCl, voff8, fm0 + k * 2 * NN * 8);
           });
         }
         const rsrc_t rMSs = make_rsrc(ms_base, push ? 2 * kHalfElems * 16u : 0u);
